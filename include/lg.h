@@ -1,0 +1,233 @@
+/*
+ * lg.h -- C ABI of the MI355X docking hot path.
+ *
+ * The calls follow the paper's statement of the virtual-screening problem
+ * (Sec. 2): identify a docking site (lg_load_pocket), dock every ligand of a
+ * bucket into it, i.e. estimate the 3D placement of its atoms
+ * (lg_dock_batch), evaluate the interaction strength and rank the library
+ * (lg_score), and refine the best poses locally (lg_refine).  Buckets of
+ * ligands of similar atom and rotamer counts, each docked by a kernel
+ * instantiated for its size class with a bucket size derived from occupancy,
+ * are the paper's out-of-kernel optimisation (Sec. 3, Eq. 1); lg_dock_batch
+ * with LG_BUCKETED is its GPU-side form.
+ *
+ * Conventions (all entry points):
+ *  - Pointers marked "device" are device memory; "host" are host memory.
+ *    The caller owns every array it passes; the library never frees them.
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream) and is
+ *    asynchronous: keep buffers alive until the stream has completed.
+ *  - Every call returns an lg_status; nothing throws across the ABI and
+ *    nothing aborts.  Argument and limit checks are synchronous and return
+ *    before any work is enqueued.  HIP errors map to LG_ERR_DEVICE and are
+ *    reported by the call that observes them.  lg_last_error() gives a
+ *    message for the last failing call of the calling thread.
+ *  - Coordinates are Angstrom, FP32.  Arithmetic is FP32 with explicit fma
+ *    (no contraction); given the same inputs, results are bitwise
+ *    reproducible run to run and identical between LG_PLAIN and LG_BUCKETED.
+ */
+#ifndef LG_H_
+#define LG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LG_OK = 0,
+  LG_ERR_INVALID_ARG = -1,   /* null pointer, bad size, inconsistent offsets */
+  LG_ERR_LIMIT = -2,         /* a size beyond the limits below */
+  LG_ERR_OUT_OF_MEMORY = -3, /* device workspace could not be allocated */
+  LG_ERR_DEVICE = -4,        /* a HIP call failed */
+  LG_ERR_UNSUPPORTED = -5    /* no gfx950 device, or an unsupported option */
+} lg_status;
+
+enum { LG_NEAREST = 0, LG_TRILINEAR = 1 };
+enum { LG_PLAIN = 0, LG_BUCKETED = 1 };
+
+#define LG_MAX_ATOMS 256      /* atoms per ligand */
+#define LG_MAX_TORSIONS 32    /* rotatable bonds per ligand (frag_mask width) */
+#define LG_MAX_SAMPLES 1024   /* angle or translation samples per scan */
+#define LG_MAX_RESTARTS 65536
+
+/* Docking site (Sec. 2): a node-centred grid of float32 values, x fastest,
+ * node (ix,iy,iz) at origin + (ix,iy,iz)*spacing.  Nearest lookups take node
+ * (int)f per axis with f = fma(x - origin, inv_spacing, 0.5) when 0 <= f < n on
+ * every axis; trilinear lookups need 0 <= (x - origin)*inv_spacing < n-1 on every
+ * axis.  Positions outside either rule score out_value (zero gradient).
+ * Restart offsets are relative to `center`. */
+typedef struct {
+  int32_t nx, ny, nz;        /* 2..1024 each */
+  float spacing;             /* Angstrom, > 0 */
+  float inv_spacing;         /* the FP32 value of 1/spacing every lookup uses */
+  float origin[3];
+  float center[3];
+  float out_value;
+} lg_pocket_desc;
+
+typedef struct lg_pocket_s* lg_pocket;
+
+/* A batch of ligands (or of poses of ligands), CSR + SoA.  Ligand i owns atoms
+ * [atom_offset[i], atom_offset[i+1]) and rotatable bonds [tors_offset[i],
+ * tors_offset[i+1]).  Rotamers (Sec. 3) are the moving fragments F_k: bit k of
+ * frag_mask[a] says that atom a moves with bond k; F_k holds the moving-side
+ * atom b_k.  Bond k is (a_k, b_k) = (static-side atom, moving-side atom), local
+ * atom ids.  Bonds are scanned in the order given.
+ *   n                 number of ligands (0 is allowed: nothing to do)
+ *   total_atoms       host value = atom_offset[n]
+ *   total_torsions    host value = tors_offset[n]
+ *   atom_offset_host  optional host copy of atom_offset; when NULL the library
+ *   tors_offset_host  validates on the device (one small synchronous read-back)
+ * Limits: 1 <= atoms <= LG_MAX_ATOMS and 0 <= bonds <= LG_MAX_TORSIONS per
+ * ligand; local ids in range. */
+typedef struct {
+  int32_t n;
+  int32_t total_atoms;
+  int32_t total_torsions;
+  const int32_t* atom_offset;      /* device [n+1] */
+  const int32_t* tors_offset;      /* device [n+1] */
+  const float* x;                  /* device [total_atoms] */
+  const float* y;
+  const float* z;
+  const uint32_t* frag_mask;       /* device [total_atoms] */
+  const int32_t* tors_atoms;       /* device [2*total_torsions] (a_k, b_k) */
+  const float* inv_bond_len;       /* device [total_torsions] FP32 of 1/|x_b - x_a| of the input */
+  const float* ref_point;          /* device [3n] rigid-body pivot P0 (e.g. the centroid) */
+  const int32_t* atom_offset_host; /* host [n+1] or NULL */
+  const int32_t* tors_offset_host; /* host [n+1] or NULL */
+} lg_ligands;
+
+/* Docking parameters.  Per restart r the ligand is placed at
+ * M_r (x0 - P0) + center + t_r, then `sweeps` times: rotation scans about the
+ * lab x, y, z axes through the pivot, translation scans along x, y, z, then a
+ * greedy scan of every rotatable bond with an intramolecular clash check.
+ * Sample j of a rotation or torsion scan turns by 2*pi*j/A (angle_table row j);
+ * sample j of a translation scan shifts by trans_step*(j < T/2 ? j : j - T).
+ * Sample 0 is the current pose.  Each scan keeps its best admissible sample
+ * (nearest-voxel score sum; equal scores keep the lowest j).  A torsion sample
+ * is admissible when every pair (moving atom of F_k other than b_k, atom
+ * outside F_k other than a_k) is at squared distance >= clash_dist2.  The final
+ * score of a restart is the trilinear score sum in atom order; the top_k
+ * restarts by final score (equal scores: lower r) are returned. */
+typedef struct {
+  int32_t restarts;          /* R, 1..LG_MAX_RESTARTS */
+  int32_t angle_samples;     /* A, 1..LG_MAX_SAMPLES */
+  int32_t trans_samples;     /* T, 1..LG_MAX_SAMPLES */
+  int32_t sweeps;            /* S, >= 0 */
+  int32_t top_k;             /* 1..R */
+  int32_t mode;              /* LG_PLAIN (one launch per ligand) or LG_BUCKETED */
+  float trans_step;          /* Angstrom */
+  float clash_dist2;         /* squared Angstrom */
+  const float* restart_table;/* device [R][12]: row-major rotation, then offset */
+  const float* angle_table;  /* device [A][2]: (cos, sin) of 2*pi*j/A */
+} lg_dock_params;
+
+/* Docking outputs (device).  Rank q of ligand i: score[i*top_k + q],
+ * restart_id[i*top_k + q]; its pose atom a (local id) sits at
+ * top_k*atom_offset[i] + q*N_i + a of x/y/z.  Optional: all_scores [n*R] final
+ * score of every restart; trace [n][R][sweeps][6+trace_kmax] the selected
+ * sample of every scan (rotations x,y,z, translations x,y,z, bonds in order;
+ * unused columns untouched), with trace_kmax >= the largest bond count. */
+typedef struct {
+  float* score;
+  int32_t* restart_id;
+  float* x;
+  float* y;
+  float* z;
+  float* all_scores;         /* optional */
+  int16_t* trace;            /* optional */
+  int32_t trace_kmax;
+} lg_dock_out;
+
+/* Load a docking site: copies the grid (host or device memory, per
+ * grid_is_device) into a library-owned device copy kept for the handle's
+ * life.  *out receives the handle; the call synchronises `stream`. */
+lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t grid_is_device,
+                         void* stream, lg_pocket* out);
+
+/* Free a handle, its grid copy and its workspace (after synchronising the
+ * device).  NULL is a no-op. */
+lg_status lg_free_pocket(lg_pocket pocket);
+
+/* Dock a batch of ligands (Sec. 2 "dock", Sec. 3 buckets).  LG_PLAIN launches
+ * one kernel per ligand sized for the largest class; LG_BUCKETED classifies
+ * ligands on the device by (atoms, bonds) into size buckets, docks every bucket
+ * in one persistent launch of its class kernel pulling (ligand, restart) items
+ * from a device queue, and replays the whole sequence as one HIP graph.
+ * Workspace grows with R * total_atoms and is held by the pocket handle: calls
+ * on one handle must not overlap. */
+lg_status lg_dock_batch(lg_pocket pocket, const lg_ligands* ligands, const lg_dock_params* params,
+                        const lg_dock_out* out, void* stream);
+
+/* Score poses (Sec. 2 "evaluate the interaction strength", "rank").  Each
+ * ligand of `poses` is one pose.  interp = LG_NEAREST or LG_TRILINEAR; score[i]
+ * = sum over its atoms in atom order.  grad (optional, trilinear only): per
+ * pose 6+K_i values at 6*i + tors_offset[i]: d(score)/d(t[3], omega[3],
+ * theta[K]) at zero for the local move (torsions about the current bond axes,
+ * rotation omega about ref_point, translation t), i.e. sum g, sum (x-P) x g,
+ * u_k . sum_{F_k} (x - x_{a_k}) x g with g the trilinear gradient and u_k the
+ * unit bond axis.  top_m > 0: top_idx / top_score (device [top_m]) receive the
+ * global ranking (score descending, equal scores: lower index). */
+lg_status lg_score(lg_pocket pocket, const lg_ligands* poses, int32_t interp, float* score, float* grad,
+                   int32_t top_m, int32_t* top_idx, float* top_score, void* stream);
+
+/* Local refinement of poses by gradient ascent on the trilinear score.  Each
+ * step: gradient at the current pose, step = (eta_t*g_t, eta_w*g_w,
+ * eta_th*g_th) clipped to norm clip_t, norm clip_w and per-bond clip_th,
+ * applied as the local move of lg_score; a step that makes an intramolecular
+ * clash (any pair separated by a rotatable bond, other than the bond's own
+ * axis atoms, closer than sqrt(clash_dist2)) is rejected and the pose kept.
+ * The best-scoring pose seen (including the input) is returned. */
+typedef struct {
+  int32_t steps;
+  float eta_t, eta_w, eta_th;
+  float clip_t, clip_w, clip_th;
+  float clash_dist2;
+} lg_refine_params;
+
+lg_status lg_refine(lg_pocket pocket, const lg_ligands* poses, const lg_refine_params* params,
+                    float* x_out, float* y_out, float* z_out, float* score_out, void* stream);
+
+/* Tuning of the bucketed path; the autotuner sets it, the defaults work.
+ * Ligands go to bucket (atom cluster, rotamer cluster): atom cluster c holds
+ * atoms <= atom_bounds[c] (first match), rotamer cluster c bonds <=
+ * rot_bounds[c]; the last cluster of each takes the rest.  A bucket is docked
+ * by the kernel instance for ceil(atom bound / 64) atom slots per lane, with
+ * waves_per_block[slots-1] wavefronts per block; its persistent grid is
+ * grid_scale times the resident blocks of Eq. 1.  Work items are chunks of
+ * restart_chunk restarts of one ligand. */
+typedef struct {
+  int32_t n_atom_clusters;        /* 1..16 */
+  int32_t atom_bounds[16];        /* increasing, each 1..LG_MAX_ATOMS */
+  int32_t n_rot_clusters;         /* 1..32 */
+  int32_t rot_bounds[32];         /* increasing, each 0..LG_MAX_TORSIONS */
+  int32_t waves_per_block[4];     /* each 1, 2 or 4 */
+  int32_t restart_chunk;          /* >= 1 */
+  int32_t grid_scale;             /* 1..64 */
+  int32_t plain_waves_per_block;  /* 1, 2 or 4 */
+} lg_tuning;
+
+lg_status lg_set_tuning(lg_pocket pocket, const lg_tuning* tuning);
+lg_status lg_get_tuning(lg_pocket pocket, lg_tuning* tuning);
+
+/* Eq. 1 of the paper: ligands per bucket l = b * units * t / ws, with b the
+ * resident blocks per compute unit of the class kernel, units the compute
+ * units, t the threads per block and ws the wavefront size.  Host only. */
+int64_t lg_bucket_size(int64_t blocks_per_unit, int64_t units, int64_t threads_per_block, int64_t wave_size);
+
+/* Cluster boundaries (Sec. 3): atom clusters at multiples of the wavefront
+ * size (n_clusters-1 boundaries ws, 2ws, ..., the last cluster takes the
+ * rest up to max_atoms); rotamer clusters split [0, max_rot] unevenly, finer at
+ * low counts.  Writes inclusive upper bounds into bounds[n_clusters]; returns
+ * the number written.  Host only. */
+int32_t lg_atom_clusters(int32_t n_clusters, int32_t wave_size, int32_t max_atoms, int32_t* bounds);
+int32_t lg_rotamer_clusters(int32_t n_clusters, int32_t max_rot, int32_t* bounds);
+
+const char* lg_last_error(void);
+int32_t lg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LG_H_ */

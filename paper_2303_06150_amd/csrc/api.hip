@@ -1,0 +1,533 @@
+// Host side of the C ABI: validation, pocket handles, workspace, the plain
+// per-ligand launch sequence, the bucketed persistent sequence captured as a
+// HIP graph, scoring and ranking.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lg.h"
+#include "lg_internal.h"
+
+namespace lg {
+hipError_t launch_dock_plain(int nslot, int spl, int wpb, const GridDev& G, const LigDev& Lg, const DockDev& D,
+                             int lig, hipStream_t st);
+hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
+                              const DockDev& D, const QueueDev& Q, hipStream_t st);
+hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int* blocks_per_cu);
+hipError_t launch_topk(const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid, float* ox,
+                       float* oy, float* oz, float* all_scores, hipStream_t st);
+hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, float* score, float* grad,
+                        hipStream_t st);
+hipError_t launch_rank_prep(const float* score, int n, float* keys, int32_t* vals, hipStream_t st);
+hipError_t launch_pad(const float* src, int nx, int ny, int nz, float out, float* dst, hipStream_t st);
+hipError_t launch_bucketing(const int32_t* atom_offset, const int32_t* tors_offset, int n, const ClusterBounds& cb,
+                            int32_t* cls, int32_t* counts, int32_t* start, int32_t* fill, int32_t* perm,
+                            int32_t* cursors, hipStream_t st);
+hipError_t launch_check(const int32_t* atom_offset, const int32_t* tors_offset, const int32_t* tors_atoms, int n,
+                        int total_atoms, int total_tors, int32_t* stats, hipStream_t st);
+}  // namespace lg
+
+namespace {
+
+thread_local std::string g_err;
+
+lg_status fail(lg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define LG_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(LG_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bump layout of a device workspace.
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  }
+};
+
+lg_tuning default_tuning() {
+  lg_tuning t;
+  std::memset(&t, 0, sizeof t);
+  t.n_atom_clusters = 4;
+  t.atom_bounds[0] = 64; t.atom_bounds[1] = 128; t.atom_bounds[2] = 192; t.atom_bounds[3] = 256;
+  t.n_rot_clusters = 1;
+  t.rot_bounds[0] = LG_MAX_TORSIONS;
+  for (int i = 0; i < 4; ++i) t.waves_per_block[i] = 4;
+  t.restart_chunk = 8;
+  t.grid_scale = 1;
+  t.plain_waves_per_block = 4;
+  return t;
+}
+
+int spl_for(int A, int T) {
+  int need = (std::max(A, T) + 63) / 64;
+  int spl = 1;
+  while (spl < need) spl *= 2;
+  return spl;
+}
+
+}  // namespace
+
+struct lg_pocket_s {
+  int device = 0;
+  int cus = 0;
+  lg_pocket_desc desc{};
+  float* padded = nullptr;
+  lg::GridDev grid{};
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  lg_tuning tuning = default_tuning();
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
+  hipStream_t capture = nullptr;   // graphs are captured here, then launched on the caller's stream
+};
+
+namespace {
+
+lg_status ensure_ws(lg_pocket p, size_t bytes) {
+  if (bytes <= p->ws_bytes) return LG_OK;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey.clear();
+  }
+  if (p->ws) {
+    LG_HIP(hipDeviceSynchronize());
+    LG_HIP(hipFree(p->ws));
+    p->ws = nullptr;
+    p->ws_bytes = 0;
+  }
+  size_t want = bytes + bytes / 8;
+  if (hipMalloc(&p->ws, want) != hipSuccess) {
+    (void)hipGetLastError();
+    p->ws = nullptr;
+    return fail(LG_ERR_OUT_OF_MEMORY, "workspace of %zu bytes could not be allocated", want);
+  }
+  p->ws_bytes = want;
+  return LG_OK;
+}
+
+lg_status check_ligands(const lg_ligands* L, bool need_tors) {
+  if (!L) return fail(LG_ERR_INVALID_ARG, "ligands is NULL");
+  if (L->n < 0) return fail(LG_ERR_INVALID_ARG, "n = %d < 0", L->n);
+  if (L->n == 0) return LG_OK;
+  if (!L->atom_offset || !L->tors_offset || !L->x || !L->y || !L->z || !L->ref_point)
+    return fail(LG_ERR_INVALID_ARG, "a required ligand array is NULL");
+  if (need_tors && (!L->frag_mask || (L->total_torsions > 0 && (!L->tors_atoms || !L->inv_bond_len))))
+    return fail(LG_ERR_INVALID_ARG, "a required ligand array is NULL");
+  if (L->total_atoms < L->n || L->total_torsions < 0) return fail(LG_ERR_INVALID_ARG, "bad total sizes");
+  if (L->atom_offset_host) {
+    for (int i = 0; i < L->n; ++i) {
+      int N = L->atom_offset_host[i + 1] - L->atom_offset_host[i];
+      if (N < 1 || N > LG_MAX_ATOMS) return fail(LG_ERR_LIMIT, "ligand %d has %d atoms (1..%d)", i, N, LG_MAX_ATOMS);
+    }
+    if (L->atom_offset_host[0] != 0 || L->atom_offset_host[L->n] != L->total_atoms)
+      return fail(LG_ERR_INVALID_ARG, "atom_offset does not span [0, total_atoms)");
+  }
+  if (L->tors_offset_host) {
+    for (int i = 0; i < L->n; ++i) {
+      int K = L->tors_offset_host[i + 1] - L->tors_offset_host[i];
+      if (K < 0 || K > LG_MAX_TORSIONS) return fail(LG_ERR_LIMIT, "ligand %d has %d bonds (0..%d)", i, K, LG_MAX_TORSIONS);
+    }
+    if (L->tors_offset_host[0] != 0 || L->tors_offset_host[L->n] != L->total_torsions)
+      return fail(LG_ERR_INVALID_ARG, "tors_offset does not span [0, total_torsions)");
+  }
+  return LG_OK;
+}
+
+// Device-side validation of offsets and bond ids (one small read-back).
+lg_status check_on_device(lg_pocket p, const lg_ligands* L, int32_t* dstats, hipStream_t st, int* max_atoms,
+                          int* max_tors) {
+  int32_t h[6];
+  LG_HIP(lg::launch_check(L->atom_offset, L->tors_offset, L->total_torsions > 0 ? L->tors_atoms : nullptr, L->n,
+                          L->total_atoms, L->total_torsions, dstats, st));
+  LG_HIP(hipMemcpyAsync(h, dstats, sizeof h, hipMemcpyDeviceToHost, st));
+  LG_HIP(hipStreamSynchronize(st));
+  (void)p;
+  if (h[5] > 0) return fail(LG_ERR_INVALID_ARG, "%d ligands have offsets outside [0, total] or decreasing", h[5]);
+  if (h[0] < 1 || h[1] > LG_MAX_ATOMS) return fail(LG_ERR_LIMIT, "atoms per ligand in [%d, %d], allowed 1..%d", h[0], h[1], LG_MAX_ATOMS);
+  if (h[2] < 0 || h[3] > LG_MAX_TORSIONS) return fail(LG_ERR_LIMIT, "bonds per ligand in [%d, %d], allowed 0..%d", h[2], h[3], LG_MAX_TORSIONS);
+  if (h[4] > 0) return fail(LG_ERR_INVALID_ARG, "%d rotatable bonds have atom ids out of range", h[4]);
+  *max_atoms = h[1];
+  *max_tors = h[3];
+  return LG_OK;
+}
+
+lg::LigDev lig_dev(const lg_ligands* L) {
+  lg::LigDev d;
+  d.atom_offset = L->atom_offset;
+  d.tors_offset = L->tors_offset;
+  d.x = L->x;
+  d.y = L->y;
+  d.z = L->z;
+  d.mask = L->frag_mask;
+  d.tors_atoms = L->tors_atoms;
+  d.inv_len = L->inv_bond_len;
+  d.ref = L->ref_point;
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lg_last_error(void) { return g_err.c_str(); }
+
+int32_t lg_version(void) { return 1; }
+
+int64_t lg_bucket_size(int64_t blocks_per_unit, int64_t units, int64_t threads_per_block, int64_t wave_size) {
+  if (blocks_per_unit < 0 || units < 0 || threads_per_block <= 0 || wave_size <= 0) return -1;
+  return blocks_per_unit * units * threads_per_block / wave_size;
+}
+
+int32_t lg_atom_clusters(int32_t n_clusters, int32_t wave_size, int32_t max_atoms, int32_t* bounds) {
+  if (n_clusters < 1 || wave_size < 1 || max_atoms < 1 || !bounds) return 0;
+  int c = 0;
+  for (; c < n_clusters - 1 && (c + 1) * wave_size < max_atoms; ++c) bounds[c] = (c + 1) * wave_size;
+  bounds[c++] = max_atoms;
+  return c;
+}
+
+int32_t lg_rotamer_clusters(int32_t n_clusters, int32_t max_rot, int32_t* bounds) {
+  if (n_clusters < 1 || max_rot < 0 || !bounds) return 0;
+  int c = 0, prev = -1;
+  for (int i = 0; i < n_clusters - 1; ++i) {
+    double f = (double)(i + 1) / n_clusters;
+    int b = (int)std::lround(max_rot * f * f);
+    b = std::max(b, prev + 1);
+    if (b >= max_rot) break;
+    bounds[c++] = b;
+    prev = b;
+  }
+  bounds[c++] = max_rot;
+  return c;
+}
+
+lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t grid_is_device, void* stream,
+                         lg_pocket* out) {
+  if (!desc || !grid || !out) return fail(LG_ERR_INVALID_ARG, "desc, grid and out must not be NULL");
+  *out = nullptr;
+  if (desc->nx < 2 || desc->ny < 2 || desc->nz < 2 || desc->nx > 1024 || desc->ny > 1024 || desc->nz > 1024)
+    return fail(LG_ERR_LIMIT, "grid dims %d x %d x %d outside 2..1024", desc->nx, desc->ny, desc->nz);
+  if (!(desc->spacing > 0.f) || !(desc->inv_spacing > 0.f) || !std::isfinite(desc->spacing))
+    return fail(LG_ERR_INVALID_ARG, "spacing must be positive");
+  int dev = 0;
+  LG_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  LG_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(LG_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  hipStream_t st = (hipStream_t)stream;
+  lg_pocket p = new (std::nothrow) lg_pocket_s();
+  if (!p) return fail(LG_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->device = dev;
+  p->cus = prop.multiProcessorCount;
+  p->desc = *desc;
+  const int nx = desc->nx, ny = desc->ny, nz = desc->nz;
+  const size_t padded = (size_t)(nx + 2) * (ny + 2) * (nz + 2);
+  if (hipMalloc(&p->padded, padded * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return fail(LG_ERR_OUT_OF_MEMORY, "grid allocation failed");
+  }
+  lg_status s = LG_OK;
+  if (grid_is_device) {
+    if (lg::launch_pad(grid, nx, ny, nz, desc->out_value, p->padded, st) != hipSuccess)
+      s = fail(LG_ERR_DEVICE, "pad kernel launch failed");
+  } else {
+    std::vector<float> h(padded, desc->out_value);
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        std::memcpy(&h[((size_t)(z + 1) * (ny + 2) + (y + 1)) * (nx + 2) + 1], &grid[((size_t)z * ny + y) * nx],
+                    nx * sizeof(float));
+    if (hipMemcpyAsync(p->padded, h.data(), padded * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      s = fail(LG_ERR_DEVICE, "grid upload failed");
+  }
+  if (s == LG_OK && hipStreamSynchronize(st) != hipSuccess) s = fail(LG_ERR_DEVICE, "stream synchronise failed");
+  if (s != LG_OK) {
+    (void)hipFree(p->padded);
+    delete p;
+    return s;
+  }
+  lg::GridDev& G = p->grid;
+  G.stride[0] = 1;
+  G.stride[1] = nx + 2;
+  G.stride[2] = (nx + 2) * (ny + 2);
+  G.g0 = p->padded + 1 + G.stride[1] + G.stride[2];
+  G.n[0] = nx; G.n[1] = ny; G.n[2] = nz;
+  for (int a = 0; a < 3; ++a) {
+    G.o[a] = desc->origin[a];
+    G.fn[a] = (float)G.n[a];
+    G.fn1[a] = (float)(G.n[a] - 1);
+  }
+  G.inv_h = desc->inv_spacing;
+  G.out = desc->out_value;
+  if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(p->padded);
+    delete p;
+    return fail(LG_ERR_DEVICE, "stream creation failed");
+  }
+  *out = p;
+  return LG_OK;
+}
+
+lg_status lg_free_pocket(lg_pocket p) {
+  if (!p) return LG_OK;
+  (void)hipDeviceSynchronize();
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->capture) (void)hipStreamDestroy(p->capture);
+  if (p->ws) (void)hipFree(p->ws);
+  if (p->padded) (void)hipFree(p->padded);
+  delete p;
+  return LG_OK;
+}
+
+lg_status lg_set_tuning(lg_pocket p, const lg_tuning* t) {
+  if (!p || !t) return fail(LG_ERR_INVALID_ARG, "pocket and tuning must not be NULL");
+  if (t->n_atom_clusters < 1 || t->n_atom_clusters > 16 || t->n_rot_clusters < 1 || t->n_rot_clusters > 32)
+    return fail(LG_ERR_INVALID_ARG, "cluster counts out of range");
+  for (int c = 0; c < t->n_atom_clusters; ++c)
+    if (t->atom_bounds[c] < 1 || t->atom_bounds[c] > LG_MAX_ATOMS || (c && t->atom_bounds[c] <= t->atom_bounds[c - 1]))
+      return fail(LG_ERR_INVALID_ARG, "atom bounds must increase within 1..%d", LG_MAX_ATOMS);
+  for (int c = 0; c < t->n_rot_clusters; ++c)
+    if (t->rot_bounds[c] < 0 || t->rot_bounds[c] > LG_MAX_TORSIONS || (c && t->rot_bounds[c] <= t->rot_bounds[c - 1]))
+      return fail(LG_ERR_INVALID_ARG, "rotamer bounds must increase within 0..%d", LG_MAX_TORSIONS);
+  for (int i = 0; i < 4; ++i)
+    if (t->waves_per_block[i] != 1 && t->waves_per_block[i] != 2 && t->waves_per_block[i] != 4)
+      return fail(LG_ERR_INVALID_ARG, "waves_per_block must be 1, 2 or 4");
+  if (t->plain_waves_per_block != 1 && t->plain_waves_per_block != 2 && t->plain_waves_per_block != 4)
+    return fail(LG_ERR_INVALID_ARG, "plain_waves_per_block must be 1, 2 or 4");
+  if (t->restart_chunk < 1 || t->grid_scale < 1 || t->grid_scale > 64)
+    return fail(LG_ERR_INVALID_ARG, "restart_chunk >= 1 and grid_scale in 1..64");
+  p->tuning = *t;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey.clear();
+  }
+  return LG_OK;
+}
+
+lg_status lg_get_tuning(lg_pocket p, lg_tuning* t) {
+  if (!p || !t) return fail(LG_ERR_INVALID_ARG, "pocket and tuning must not be NULL");
+  *t = p->tuning;
+  return LG_OK;
+}
+
+lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* P, const lg_dock_out* O,
+                        void* stream) {
+  if (!p || !P || !O) return fail(LG_ERR_INVALID_ARG, "pocket, params and out must not be NULL");
+  lg_status s = check_ligands(L, true);
+  if (s != LG_OK) return s;
+  if (P->restarts < 1 || P->restarts > LG_MAX_RESTARTS) return fail(LG_ERR_LIMIT, "restarts %d outside 1..%d", P->restarts, LG_MAX_RESTARTS);
+  if (P->angle_samples < 1 || P->angle_samples > LG_MAX_SAMPLES || P->trans_samples < 1 || P->trans_samples > LG_MAX_SAMPLES)
+    return fail(LG_ERR_LIMIT, "samples per scan outside 1..%d", LG_MAX_SAMPLES);
+  if (P->sweeps < 0) return fail(LG_ERR_INVALID_ARG, "sweeps < 0");
+  if (P->top_k < 1 || P->top_k > P->restarts) return fail(LG_ERR_INVALID_ARG, "top_k %d outside 1..R", P->top_k);
+  if (P->mode != LG_PLAIN && P->mode != LG_BUCKETED) return fail(LG_ERR_INVALID_ARG, "unknown mode %d", P->mode);
+  if (!P->restart_table || !P->angle_table) return fail(LG_ERR_INVALID_ARG, "restart_table and angle_table are required");
+  if (!std::isfinite(P->trans_step) || !std::isfinite(P->clash_dist2)) return fail(LG_ERR_INVALID_ARG, "non-finite step or clash distance");
+  if (L->n > 0 && (!O->score || !O->restart_id || !O->x || !O->y || !O->z))
+    return fail(LG_ERR_INVALID_ARG, "score, restart_id and x/y/z outputs are required");
+  if (L->n == 0) return LG_OK;
+  if ((long long)P->restarts * L->total_atoms > (1LL << 40)) return fail(LG_ERR_LIMIT, "R * total_atoms too large");
+  hipStream_t st = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+
+  const int n = L->n, R = P->restarts;
+  const lg_tuning& tu = p->tuning;
+  const int B = tu.n_atom_clusters * tu.n_rot_clusters;
+  Layout lay;
+  const size_t o_stats = lay.take(16 * sizeof(int32_t));
+  const size_t o_final = lay.take((size_t)n * R * sizeof(float));
+  const size_t o_wp = lay.take((size_t)3 * R * L->total_atoms * sizeof(float));
+  const size_t o_cls = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_perm = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_cnt = lay.take((size_t)(4 * B + 1) * sizeof(int32_t));
+  s = ensure_ws(p, lay.off);
+  if (s != LG_OK) return s;
+  char* ws = (char*)p->ws;
+  int32_t* stats = (int32_t*)(ws + o_stats);
+
+  int max_atoms = 0, max_tors = 0;
+  s = check_on_device(p, L, stats, st, &max_atoms, &max_tors);
+  if (s != LG_OK) return s;
+  if (O->trace && O->trace_kmax < max_tors) return fail(LG_ERR_INVALID_ARG, "trace_kmax %d < largest bond count %d", O->trace_kmax, max_tors);
+
+  lg::DockDev D;
+  D.R = R;
+  D.A = P->angle_samples;
+  D.T = P->trans_samples;
+  D.S = P->sweeps;
+  D.delta = P->trans_step;
+  D.clash2 = P->clash_dist2;
+  for (int a = 0; a < 3; ++a) D.c[a] = p->desc.center[a];
+  D.restarts = P->restart_table;
+  D.angles = P->angle_table;
+  D.final_scores = (float*)(ws + o_final);
+  D.wpx = (float*)(ws + o_wp);
+  D.wpy = D.wpx + (size_t)R * L->total_atoms;
+  D.wpz = D.wpy + (size_t)R * L->total_atoms;
+  D.trace = O->trace;
+  D.trace_w = 6 + (O->trace ? O->trace_kmax : 0);
+  const lg::LigDev Lg = lig_dev(L);
+  const int spl = spl_for(D.A, D.T);
+  if (spl > 16) return fail(LG_ERR_LIMIT, "samples per lane %d > 16", spl);
+
+  if (P->mode == LG_PLAIN) {
+    // the plain method: one launch per ligand, kernel sized for the largest class
+    const int nslot = LG_MAX_ATOMS / 64;
+    for (int i = 0; i < n; ++i)
+      LG_HIP(lg::launch_dock_plain(nslot, spl, tu.plain_waves_per_block, p->grid, Lg, D, i, st));
+    LG_HIP(lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, st));
+    return LG_OK;
+  }
+
+  // bucketed: classify / scan / scatter on the device, one persistent launch per
+  // bucket, top-k; captured once as a graph and replayed for identical calls
+  int32_t* cls = (int32_t*)(ws + o_cls);
+  int32_t* perm = (int32_t*)(ws + o_perm);
+  int32_t* counts = (int32_t*)(ws + o_cnt);
+  int32_t* start = counts + B;
+  int32_t* fill = start + B + 1;
+  int32_t* cursors = fill + B;
+  std::vector<uint64_t> key = {(uint64_t)n, (uint64_t)L->total_atoms,
+                               (uint64_t)L->total_torsions, (uint64_t)(uintptr_t)p->ws,
+                               (uint64_t)R, (uint64_t)D.A, (uint64_t)D.T, (uint64_t)D.S, (uint64_t)P->top_k};
+  const void* ptrs[] = {L->atom_offset, L->tors_offset, L->x, L->y, L->z, L->frag_mask, L->tors_atoms,
+                        L->inv_bond_len, L->ref_point, P->restart_table, P->angle_table, O->score,
+                        O->restart_id, O->x, O->y, O->z, O->all_scores, O->trace};
+  for (const void* q : ptrs) key.push_back((uint64_t)(uintptr_t)q);
+  uint32_t fb[3];
+  std::memcpy(&fb[0], &D.delta, 4);
+  std::memcpy(&fb[1], &D.clash2, 4);
+  fb[2] = (uint32_t)O->trace_kmax;
+  for (uint32_t v : fb) key.push_back(v);
+
+  if (!p->gexec || key != p->gkey) {
+    if (p->gexec) {
+      (void)hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+      p->gkey.clear();
+    }
+    lg::ClusterBounds cb;
+    std::memset(&cb, 0, sizeof cb);
+    cb.na = tu.n_atom_clusters;
+    cb.nr = tu.n_rot_clusters;
+    for (int c = 0; c < cb.na; ++c) cb.atom[c] = tu.atom_bounds[c];
+    for (int c = 0; c < cb.nr; ++c) cb.rot[c] = tu.rot_bounds[c];
+    // every atom cluster must fit its kernel instance: the last one takes the rest
+    cb.atom[cb.na - 1] = LG_MAX_ATOMS;
+    // Eq. 1: resident blocks per CU of each instance; the persistent grid
+    struct Launch { int nslot, wpb, blocks, bucket; };
+    std::vector<Launch> launches;
+    for (int ca = cb.na - 1; ca >= 0; --ca) {
+      const int nslot = (cb.atom[ca] + 63) / 64;
+      const int wpb = tu.waves_per_block[nslot - 1];
+      int bpc = 0;
+      LG_HIP(lg::occupancy_dock_bucket(nslot, spl, wpb, &bpc));
+      if (bpc < 1) return fail(LG_ERR_DEVICE, "kernel instance (%d slots, %d samples/lane) cannot be resident", nslot, spl);
+      for (int cr = cb.nr - 1; cr >= 0; --cr)
+        launches.push_back({nslot, wpb, bpc * p->cus * tu.grid_scale, ca * cb.nr + cr});
+    }
+    hipGraph_t graph = nullptr;
+    hipStream_t cs = p->capture;
+    LG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    hipError_t e = lg::launch_bucketing(L->atom_offset, L->tors_offset, n, cb, cls, counts, start, fill, perm, cursors, cs);
+    for (const Launch& l : launches) {
+      if (e != hipSuccess) break;
+      lg::QueueDev Q{perm, start, cursors, l.bucket, tu.restart_chunk};
+      e = lg::launch_dock_bucket(l.nslot, spl, l.wpb, l.blocks, p->grid, Lg, D, Q, cs);
+    }
+    if (e == hipSuccess) e = lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(LG_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipError_t e3 = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      p->gexec = nullptr;
+      return fail(LG_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e3));
+    }
+    p->gkey = key;
+  }
+  LG_HIP(hipGraphLaunch(p->gexec, st));
+  return LG_OK;
+}
+
+lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, float* score, float* grad, int32_t top_m,
+                   int32_t* top_idx, float* top_score, void* stream) {
+  if (!p) return fail(LG_ERR_INVALID_ARG, "pocket is NULL");
+  lg_status s = check_ligands(L, grad != nullptr);
+  if (s != LG_OK) return s;
+  if (interp != LG_NEAREST && interp != LG_TRILINEAR) return fail(LG_ERR_INVALID_ARG, "interp must be LG_NEAREST or LG_TRILINEAR");
+  if (grad && interp != LG_TRILINEAR) return fail(LG_ERR_INVALID_ARG, "gradients need LG_TRILINEAR");
+  if (L->n > 0 && !score) return fail(LG_ERR_INVALID_ARG, "score is NULL");
+  if (top_m < 0 || top_m > L->n) return fail(LG_ERR_INVALID_ARG, "top_m %d outside 0..n", top_m);
+  if (top_m > 0 && (!top_idx || !top_score)) return fail(LG_ERR_INVALID_ARG, "top_idx and top_score are required for top_m > 0");
+  if (L->n == 0) return LG_OK;
+  hipStream_t st = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+  const int n = L->n;
+  size_t sort_tmp = 0;
+  if (top_m > 0)
+    LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_tmp, (const float*)nullptr, (float*)nullptr,
+                                                          (const int32_t*)nullptr, (int32_t*)nullptr, n, 0, 32, st));
+  Layout lay;
+  const size_t o_stats = lay.take(16 * sizeof(int32_t));
+  const size_t o_k0 = lay.take((size_t)n * sizeof(float));
+  const size_t o_k1 = lay.take((size_t)n * sizeof(float));
+  const size_t o_v0 = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_v1 = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_tmp = lay.take(sort_tmp + 16);
+  s = ensure_ws(p, lay.off);
+  if (s != LG_OK) return s;
+  char* ws = (char*)p->ws;
+  int max_atoms = 0, max_tors = 0;
+  s = check_on_device(p, L, (int32_t*)(ws + o_stats), st, &max_atoms, &max_tors);
+  if (s != LG_OK) return s;
+  LG_HIP(lg::launch_score(p->grid, lig_dev(L), n, interp, score, grad, st));
+  if (top_m > 0) {
+    float* k0 = (float*)(ws + o_k0);
+    float* k1 = (float*)(ws + o_k1);
+    int32_t* v0 = (int32_t*)(ws + o_v0);
+    int32_t* v1 = (int32_t*)(ws + o_v1);
+    LG_HIP(lg::launch_rank_prep(score, n, k0, v0, st));
+    LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(ws + o_tmp, sort_tmp, k0, k1, v0, v1, n, 0, 32, st));
+    LG_HIP(hipMemcpyAsync(top_idx, v1, (size_t)top_m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    LG_HIP(hipMemcpyAsync(top_score, k1, (size_t)top_m * sizeof(float), hipMemcpyDeviceToDevice, st));
+  }
+  return LG_OK;
+}
+
+lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* params, float* x_out, float* y_out,
+                    float* z_out, float* score_out, void* stream) {
+  (void)p; (void)L; (void)params; (void)x_out; (void)y_out; (void)z_out; (void)score_out; (void)stream;
+  return fail(LG_ERR_UNSUPPORTED, "lg_refine is not available in this build");
+}
+
+}  // extern "C"

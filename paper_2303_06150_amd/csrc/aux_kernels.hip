@@ -1,0 +1,263 @@
+// Pose scoring (nearest / trilinear + force-torque adjoint), pocket padding,
+// device-side input preparation (classify / scan / scatter into size buckets)
+// and validation kernels.
+#include "lg_internal.h"
+
+#include <climits>
+
+namespace lg {
+
+__device__ __forceinline__ float nearest_s(const GridDev& G, float x, float y, float z) {
+  int ix = clamp_node(fmaf(x - G.o[0], G.inv_h, 0.5f), G.fn[0]);
+  int iy = clamp_node(fmaf(y - G.o[1], G.inv_h, 0.5f), G.fn[1]);
+  int iz = clamp_node(fmaf(z - G.o[2], G.inv_h, 0.5f), G.fn[2]);
+  return G.g0[ix + iy * G.stride[1] + iz * G.stride[2]];
+}
+
+__device__ __forceinline__ float trilinear_s(const GridDev& G, float x, float y, float z, float* g) {
+  float f0 = (x - G.o[0]) * G.inv_h, f1 = (y - G.o[1]) * G.inv_h, f2 = (z - G.o[2]) * G.inv_h;
+  bool in = f0 >= 0.f && f0 < G.fn1[0] && f1 >= 0.f && f1 < G.fn1[1] && f2 >= 0.f && f2 < G.fn1[2];
+  if (!in) {
+    g[0] = g[1] = g[2] = 0.f;
+    return G.out;
+  }
+  int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
+  float w0 = f0 - (float)i0, w1 = f1 - (float)i1, w2 = f2 - (float)i2;
+  const int s1 = G.stride[1], s2 = G.stride[2];
+  const float* p = G.g0 + i0 + i1 * s1 + i2 * s2;
+  float c000 = p[0], c100 = p[1], c010 = p[s1], c110 = p[s1 + 1];
+  float c001 = p[s2], c101 = p[s2 + 1], c011 = p[s2 + s1], c111 = p[s2 + s1 + 1];
+  float c00 = fmaf(w0, c100 - c000, c000), c10 = fmaf(w0, c110 - c010, c010);
+  float c01 = fmaf(w0, c101 - c001, c001), c11 = fmaf(w0, c111 - c011, c011);
+  float c0 = fmaf(w1, c10 - c00, c00), c1 = fmaf(w1, c11 - c01, c01);
+  float e00 = c100 - c000, e10 = c110 - c010, e01 = c101 - c001, e11 = c111 - c011;
+  float e0 = fmaf(w1, e10 - e00, e00), e1 = fmaf(w1, e11 - e01, e01);
+  g[0] = fmaf(w2, e1 - e0, e0) * G.inv_h;
+  float d0 = c10 - c00, d1 = c11 - c01;
+  g[1] = fmaf(w2, d1 - d0, d0) * G.inv_h;
+  g[2] = (c1 - c0) * G.inv_h;
+  return fmaf(w2, c1 - c0, c0);
+}
+
+template <int NSLOT>
+__device__ __forceinline__ float atom_value_s(const float (&v)[NSLOT], int a) {
+  // one readlane per slot, selected on the scalar side (no dynamic register index)
+  const int slot = a >> 6, l = a & 63;
+  int r = __builtin_amdgcn_readlane(__float_as_int(v[0]), l);
+#pragma unroll
+  for (int s = 1; s < NSLOT; ++s) {
+    const int rs = __builtin_amdgcn_readlane(__float_as_int(v[s]), l);
+    r = slot == s ? rs : r;
+  }
+  return __int_as_float(r);
+}
+
+// One wavefront per pose: score = sum over atoms in atom order; optional
+// gradient with respect to (t, omega, theta) at zero (force / torque form).
+__global__ __launch_bounds__(256) void score_kernel(GridDev G, LigDev P, int n, int interp, float* score,
+                                                     float* grad) {
+  constexpr int NS = 4;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
+  const int i = blockIdx.x * nwaves + wave;
+  if (i >= n) return;
+  const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[i]);
+  const int N = __builtin_amdgcn_readfirstlane(P.atom_offset[i + 1]) - abase;
+  float x[3][NS], g[3][NS], v[NS];
+  uint32_t mk[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int a = s * 64 + lane;
+    const bool in = a < N;
+    x[0][s] = in ? P.x[abase + a] : 0.f;
+    x[1][s] = in ? P.y[abase + a] : 0.f;
+    x[2][s] = in ? P.z[abase + a] : 0.f;
+    mk[s] = in ? P.mask[abase + a] : 0u;
+    float gg[3] = {0.f, 0.f, 0.f};
+    v[s] = 0.f;
+    if (in) v[s] = interp == LG_TRILINEAR ? trilinear_s(G, x[0][s], x[1][s], x[2][s], gg) : nearest_s(G, x[0][s], x[1][s], x[2][s]);
+    g[0][s] = gg[0]; g[1][s] = gg[1]; g[2][s] = gg[2];
+  }
+  float total = 0.f;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int cnt = min(64, N - s * 64);
+    for (int l = 0; l < cnt; ++l) total = total + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[s]), l));
+  }
+  if (lane == 0) score[i] = total;
+  if (!grad || interp != LG_TRILINEAR) return;
+  const int toff = __builtin_amdgcn_readfirstlane(P.tors_offset[i]);
+  const int K = __builtin_amdgcn_readfirstlane(P.tors_offset[i + 1]) - toff;
+  const float Px = P.ref[3 * i], Py = P.ref[3 * i + 1], Pz = P.ref[3 * i + 2];
+  float f[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    float rx = x[0][s] - Px, ry = x[1][s] - Py, rz = x[2][s] - Pz;
+    f[0] += g[0][s]; f[1] += g[1][s]; f[2] += g[2][s];
+    tq[0] += ry * g[2][s] - rz * g[1][s];
+    tq[1] += rz * g[0][s] - rx * g[2][s];
+    tq[2] += rx * g[1][s] - ry * g[0][s];
+  }
+  float* out = grad + 6 * (size_t)i + toff;
+  float red[6];
+  for (int c = 0; c < 3; ++c) { red[c] = wave_sum(f[c]); red[3 + c] = wave_sum(tq[c]); }
+  if (lane == 0)
+    for (int c = 0; c < 6; ++c) out[c] = red[c];
+  for (int k = 0; k < K; ++k) {
+    const int a = __builtin_amdgcn_readfirstlane(P.tors_atoms[2 * (toff + k)]);
+    const int b = __builtin_amdgcn_readfirstlane(P.tors_atoms[2 * (toff + k) + 1]);
+    const float xa = atom_value_s(x[0], a), ya = atom_value_s(x[1], a), za = atom_value_s(x[2], a);
+    float ux = atom_value_s(x[0], b) - xa, uy = atom_value_s(x[1], b) - ya, uz = atom_value_s(x[2], b) - za;
+    const float inv = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+    ux *= inv; uy *= inv; uz *= inv;
+    float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if ((mk[s] >> k) & 1u) {
+        float rx = x[0][s] - xa, ry = x[1][s] - ya, rz = x[2][s] - za;
+        t[0] += ry * g[2][s] - rz * g[1][s];
+        t[1] += rz * g[0][s] - rx * g[2][s];
+        t[2] += rx * g[1][s] - ry * g[0][s];
+      }
+    }
+    const float tk = ux * wave_sum(t[0]) + uy * wave_sum(t[1]) + uz * wave_sum(t[2]);
+    if (lane == 0) out[6 + k] = tk;
+  }
+}
+
+hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, float* score, float* grad,
+                        hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int wpb = 4;
+  hipLaunchKernelGGL(score_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), 0, st, G, P, n, interp, score, grad);
+  return hipGetLastError();
+}
+
+// Canonical sort keys (+0 for -0) and identity values for the global ranking.
+__global__ void rank_prep_kernel(const float* score, int n, float* keys, int32_t* vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    keys[i] = score[i] + 0.0f;
+    vals[i] = i;
+  }
+}
+
+hipError_t launch_rank_prep(const float* score, int n, float* keys, int32_t* vals, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, score, n, keys, vals);
+  return hipGetLastError();
+}
+
+// Copy the grid into the padded layout with an out_value border.
+__global__ void pad_kernel(const float* src, int nx, int ny, int nz, float out, float* dst) {
+  const long long px = nx + 2, py = ny + 2, pz = nz + 2;
+  const long long total = px * py * pz;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const long long ix = idx % px, iy = (idx / px) % py, iz = idx / (px * py);
+    const bool in = ix >= 1 && ix <= nx && iy >= 1 && iy <= ny && iz >= 1 && iz <= nz;
+    dst[idx] = in ? src[((iz - 1) * ny + (iy - 1)) * nx + (ix - 1)] : out;
+  }
+}
+
+hipError_t launch_pad(const float* src, int nx, int ny, int nz, float out, float* dst, hipStream_t st) {
+  hipLaunchKernelGGL(pad_kernel, dim3(1024), dim3(256), 0, st, src, nx, ny, nz, out, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- input preparation (buckets)
+__global__ void zero_kernel(int32_t* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+__global__ void classify_kernel(const int32_t* atom_offset, const int32_t* tors_offset, int n, ClusterBounds cb,
+                                int32_t* cls, int32_t* counts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int N = atom_offset[i + 1] - atom_offset[i];
+  const int K = tors_offset[i + 1] - tors_offset[i];
+  int ca = cb.na - 1, cr = cb.nr - 1;
+  for (int c = cb.na - 1; c >= 0; --c)
+    if (N <= cb.atom[c]) ca = c;
+  for (int c = cb.nr - 1; c >= 0; --c)
+    if (K <= cb.rot[c]) cr = c;
+  const int b = ca * cb.nr + cr;
+  cls[i] = b;
+  atomicAdd(&counts[b], 1);
+}
+
+__global__ void bucket_scan_kernel(const int32_t* counts, int B, int32_t* start, int32_t* fill) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int s = 0;
+    for (int b = 0; b < B; ++b) {
+      start[b] = s;
+      s += counts[b];
+      fill[b] = 0;
+    }
+    start[B] = s;
+  }
+}
+
+__global__ void scatter_kernel(const int32_t* cls, int n, const int32_t* start, int32_t* fill, int32_t* perm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = cls[i];
+  perm[start[b] + atomicAdd(&fill[b], 1)] = i;
+}
+
+hipError_t launch_bucketing(const int32_t* atom_offset, const int32_t* tors_offset, int n, const ClusterBounds& cb,
+                            int32_t* cls, int32_t* counts, int32_t* start, int32_t* fill, int32_t* perm,
+                            int32_t* cursors, hipStream_t st) {
+  const int B = cb.na * cb.nr;
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, st, counts, B);
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(256), 0, st, cursors, B);
+  if (n > 0) hipLaunchKernelGGL(classify_kernel, dim3((n + 255) / 256), dim3(256), 0, st, atom_offset, tors_offset, n, cb, cls, counts);
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(64), 0, st, counts, B, start, fill);
+  if (n > 0) hipLaunchKernelGGL(scatter_kernel, dim3((n + 255) / 256), dim3(256), 0, st, cls, n, start, fill, perm);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- device validation
+// stats: [0] min atoms, [1] max atoms, [2] min bonds, [3] max bonds,
+//        [4] count of bad bond ids, [5] count of inconsistent offsets
+__global__ void check_kernel(const int32_t* atom_offset, const int32_t* tors_offset, const int32_t* tors_atoms,
+                             int n, int total_atoms, int total_tors, int32_t* stats) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a0 = atom_offset[i], a1 = atom_offset[i + 1];
+  const int t0 = tors_offset[i], t1 = tors_offset[i + 1];
+  const int N = a1 - a0, K = t1 - t0;
+  atomicMin(&stats[0], N);
+  atomicMax(&stats[1], N);
+  atomicMin(&stats[2], K);
+  atomicMax(&stats[3], K);
+  bool offsets_ok = a0 >= 0 && a1 <= total_atoms && t0 >= 0 && t1 <= total_tors && N >= 0 && K >= 0;
+  if (i == 0 && (a0 != 0 || t0 != 0)) offsets_ok = false;
+  if (i == n - 1 && (a1 != total_atoms || t1 != total_tors)) offsets_ok = false;
+  if (!offsets_ok) {
+    atomicAdd(&stats[5], 1);
+    return;
+  }
+  if (tors_atoms)
+    for (int k = t0; k < t1; ++k) {
+      const int a = tors_atoms[2 * k], b = tors_atoms[2 * k + 1];
+      if (a < 0 || a >= N || b < 0 || b >= N || a == b) atomicAdd(&stats[4], 1);
+    }
+}
+
+__global__ void check_init_kernel(int32_t* stats) {
+  if (threadIdx.x == 0) {
+    stats[0] = INT_MAX; stats[1] = INT_MIN; stats[2] = INT_MAX; stats[3] = INT_MIN;
+    stats[4] = 0; stats[5] = 0;
+  }
+}
+
+hipError_t launch_check(const int32_t* atom_offset, const int32_t* tors_offset, const int32_t* tors_atoms, int n,
+                        int total_atoms, int total_tors, int32_t* stats, hipStream_t st) {
+  hipLaunchKernelGGL(check_init_kernel, dim3(1), dim3(64), 0, st, stats);
+  if (n > 0)
+    hipLaunchKernelGGL(check_kernel, dim3((n + 255) / 256), dim3(256), 0, st, atom_offset, tors_offset, tors_atoms,
+                       n, total_atoms, total_tors, stats);
+  return hipGetLastError();
+}
+
+}  // namespace lg

@@ -1,0 +1,600 @@
+// Docking kernels for gfx950: restart placement, rigid rotation / translation
+// scans, greedy torsion scans with the intramolecular clash check, nearest-voxel
+// scan scores, trilinear final score, per-ligand top-k.
+//
+// Mapping.  One wavefront docks one restart (ligand, r).  A scan's samples are
+// spread over the 64 lanes (sample j = lane + 64 q, q < SPL); each lane loops
+// over the atoms of the scan, reading per-atom scan data that the wavefront
+// staged in LDS (broadcast reads), and accumulates nearest-voxel values
+// gathered from the L2-resident grid.  The pose lives in registers, atom
+// a = 64 s + lane in slot s < NSLOT.  The best sample comes from a DPP/readlane
+// reduction (lowest index among equal scores).  For torsions only the winning
+// sample is tested for clashes (lanes over the static atoms, loop over the
+// moving ones); a clashing winner is dropped and the next best taken, which
+// selects exactly the best admissible sample.
+//
+// Arithmetic contract (matches the CPU oracle bit for bit): FP32, explicit
+// fmaf, no contraction; sums of quantised grid values are exact in any order,
+// the final trilinear sum runs in atom order.
+#include "lg_internal.h"
+
+#include <climits>
+
+namespace lg {
+
+template <int NSLOT>
+struct PoseReg {
+  float x[3][NSLOT];
+  float piv[3];
+};
+
+template <int SPL>
+struct SampleReg {
+  float c[SPL], s[SPL], d[SPL];
+  uint32_t valid_a, valid_t;   // bit q: sample lane + 64 q exists
+};
+
+__device__ __forceinline__ float nearest(const GridDev& G, float x, float y, float z) {
+  int ix = clamp_node(fmaf(x - G.o[0], G.inv_h, 0.5f), G.fn[0]);
+  int iy = clamp_node(fmaf(y - G.o[1], G.inv_h, 0.5f), G.fn[1]);
+  int iz = clamp_node(fmaf(z - G.o[2], G.inv_h, 0.5f), G.fn[2]);
+  return G.g0[ix + iy * G.stride[1] + iz * G.stride[2]];
+}
+
+// Trilinear value (and gradient if g != nullptr); same op order as the oracle.
+__device__ __forceinline__ float trilinear(const GridDev& G, float x, float y, float z, float* g) {
+  float f0 = (x - G.o[0]) * G.inv_h, f1 = (y - G.o[1]) * G.inv_h, f2 = (z - G.o[2]) * G.inv_h;
+  bool in = f0 >= 0.f && f0 < G.fn1[0] && f1 >= 0.f && f1 < G.fn1[1] && f2 >= 0.f && f2 < G.fn1[2];
+  if (!in) {
+    if (g) g[0] = g[1] = g[2] = 0.f;
+    return G.out;
+  }
+  int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
+  float w0 = f0 - (float)i0, w1 = f1 - (float)i1, w2 = f2 - (float)i2;
+  const int s1 = G.stride[1], s2 = G.stride[2];
+  const float* p = G.g0 + i0 + i1 * s1 + i2 * s2;
+  float c000 = p[0], c100 = p[1], c010 = p[s1], c110 = p[s1 + 1];
+  float c001 = p[s2], c101 = p[s2 + 1], c011 = p[s2 + s1], c111 = p[s2 + s1 + 1];
+  float c00 = fmaf(w0, c100 - c000, c000), c10 = fmaf(w0, c110 - c010, c010);
+  float c01 = fmaf(w0, c101 - c001, c001), c11 = fmaf(w0, c111 - c011, c011);
+  float c0 = fmaf(w1, c10 - c00, c00), c1 = fmaf(w1, c11 - c01, c01);
+  float v = fmaf(w2, c1 - c0, c0);
+  if (g) {
+    float e00 = c100 - c000, e10 = c110 - c010, e01 = c101 - c001, e11 = c111 - c011;
+    float e0 = fmaf(w1, e10 - e00, e00), e1 = fmaf(w1, e11 - e01, e01);
+    g[0] = fmaf(w2, e1 - e0, e0) * G.inv_h;
+    float d0 = c10 - c00, d1 = c11 - c01;
+    g[1] = fmaf(w2, d1 - d0, d0) * G.inv_h;
+    g[2] = (c1 - c0) * G.inv_h;
+  }
+  return v;
+}
+
+template <int SPL>
+__device__ __forceinline__ int wave_argmax(const float (&acc)[SPL], uint32_t alive) {
+  const int lane = lane_id();
+  int best = INT_MIN, bj = INT_MAX;
+#pragma unroll
+  for (int q = 0; q < SPL; ++q) {
+    int k = orderable(acc[q]);
+    if (((alive >> q) & 1u) && k > best) { best = k; bj = lane + 64 * q; }
+  }
+  int wmax = wave_reduce_i32(best, OpMax());
+  return wave_reduce_i32(best == wmax ? bj : INT_MAX, OpMin());
+}
+
+// Value of register array v for atom a, taken from the lane that holds it.
+template <int NSLOT>
+__device__ __forceinline__ float atom_value(const float (&v)[NSLOT], int a) {
+  // one readlane per slot, selected on the scalar side (no dynamic register index)
+  const int slot = a >> 6, l = a & 63;
+  int r = __builtin_amdgcn_readlane(__float_as_int(v[0]), l);
+#pragma unroll
+  for (int s = 1; s < NSLOT; ++s) {
+    const int rs = __builtin_amdgcn_readlane(__float_as_int(v[s]), l);
+    r = slot == s ? rs : r;
+  }
+  return __int_as_float(r);
+}
+
+__device__ __forceinline__ void torsion_matrix(float ux, float uy, float uz, float c, float s, float m[9]) {
+  float t = 1.0f - c;
+  float tx = t * ux, ty = t * uy, tz = t * uz;
+  m[0] = fmaf(tx, ux, c);
+  m[4] = fmaf(ty, uy, c);
+  m[8] = fmaf(tz, uz, c);
+  m[1] = fmaf(tx, uy, -(s * uz));
+  m[3] = fmaf(tx, uy, s * uz);
+  m[2] = fmaf(tx, uz, s * uy);
+  m[6] = fmaf(tx, uz, -(s * uy));
+  m[5] = fmaf(ty, uz, -(s * ux));
+  m[7] = fmaf(ty, uz, s * ux);
+}
+
+__device__ __forceinline__ void mat_apply(const float m[9], float vx, float vy, float vz, float& y0, float& y1,
+                                          float& y2) {
+  y0 = fmaf(m[2], vz, fmaf(m[1], vy, m[0] * vx));
+  y1 = fmaf(m[5], vz, fmaf(m[4], vy, m[3] * vx));
+  y2 = fmaf(m[8], vz, fmaf(m[7], vy, m[6] * vx));
+}
+
+// ---- rigid rotation scan about lab axis E through the pivot ------------------
+template <int NSLOT, int SPL, int E>
+__device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr,
+                        const SampleReg<SPL>& sm) {
+  constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
+  const int lane = lane_id();
+  float s0 = 0.f;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    if (a < N) {
+      float vp = p.x[P][s] - p.piv[P], vq = p.x[Q][s] - p.piv[Q];
+      int ie = clamp_node(fmaf(p.x[E][s] - G.o[E], G.inv_h, 0.5f), G.fn[E]);
+      scr[a] = make_float4(vp, vq, __int_as_float(ie * G.stride[E]), 0.f);
+      s0 += nearest(G, p.x[0][s], p.x[1][s], p.x[2][s]);
+    }
+  }
+  s0 = wave_sum(s0);
+  wave_sync();
+  float acc[SPL];
+#pragma unroll
+  for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
+  const float pP = p.piv[P], pQ = p.piv[Q];
+  const float oP = G.o[P], oQ = G.o[Q], ih = G.inv_h, fnP = G.fn[P], fnQ = G.fn[Q];
+  const int sP = G.stride[P], sQ = G.stride[Q];
+  const float* g0 = G.g0;
+  for (int t = 0; t < N; ++t) {
+    const float4 d = scr[t];
+    const int part = __float_as_int(d.z);
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+      float np = fmaf(sm.c[q], d.x, -(sm.s[q] * d.y));
+      float nq = fmaf(sm.s[q], d.x, sm.c[q] * d.y);
+      float xp = pP + np, xq = pQ + nq;
+      int ip = clamp_node(fmaf(xp - oP, ih, 0.5f), fnP);
+      int iq = clamp_node(fmaf(xq - oQ, ih, 0.5f), fnQ);
+      acc[q] += g0[part + ip * sP + iq * sQ];
+    }
+  }
+  if (lane == 0) acc[0] = s0;   // sample 0 is the current pose
+  const int j = wave_argmax(acc, sm.valid_a);
+  if (j != 0) {
+    const float c = D.angles[2 * j], sn = D.angles[2 * j + 1];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      float vp = p.x[P][s] - pP, vq = p.x[Q][s] - pQ;
+      float np = fmaf(c, vp, -(sn * vq));
+      float nq = fmaf(sn, vp, c * vq);
+      p.x[P][s] = pP + np;
+      p.x[Q][s] = pQ + nq;
+    }
+  }
+  wave_sync();
+  return j;
+}
+
+// ---- rigid translation scan along lab axis E ---------------------------------
+template <int NSLOT, int SPL, int E>
+__device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr,
+                          const SampleReg<SPL>& sm) {
+  constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    if (a < N) {
+      int ip = clamp_node(fmaf(p.x[P][s] - G.o[P], G.inv_h, 0.5f), G.fn[P]);
+      int iq = clamp_node(fmaf(p.x[Q][s] - G.o[Q], G.inv_h, 0.5f), G.fn[Q]);
+      scr[a] = make_float4(p.x[E][s], __int_as_float(ip * G.stride[P] + iq * G.stride[Q]), 0.f, 0.f);
+    }
+  }
+  wave_sync();
+  float acc[SPL];
+#pragma unroll
+  for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
+  const float oE = G.o[E], ih = G.inv_h, fnE = G.fn[E];
+  const int sE = G.stride[E];
+  const float* g0 = G.g0;
+  for (int t = 0; t < N; ++t) {
+    const float4 d = scr[t];
+    const int part = __float_as_int(d.y);
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+      float xe = d.x + sm.d[q];
+      int ie = clamp_node(fmaf(xe - oE, ih, 0.5f), fnE);
+      acc[q] += g0[part + ie * sE];
+    }
+  }
+  const int j = wave_argmax(acc, sm.valid_t);
+  if (j != 0) {
+    const int m = j < D.T / 2 ? j : j - D.T;
+    const float dd = D.delta * (float)m;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) p.x[E][s] = p.x[E][s] + dd;
+    p.piv[E] = p.piv[E] + dd;
+  }
+  wave_sync();
+  return j;
+}
+
+// ---- greedy torsion scan of bond k with the clash check ----------------------
+template <int NSLOT, int SPL>
+__device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, PoseReg<NSLOT>& p, int N,
+                         int toff, int k, const uint32_t (&mk)[NSLOT], float4* scr, float4* cand,
+                         const SampleReg<SPL>& sm) {
+  const int lane = lane_id();
+  const int a = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k)]);
+  const int b = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k) + 1]);
+  const float il = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Lg.inv_len[toff + k])));
+  const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
+  const float xb = atom_value(p.x[0], b), yb = atom_value(p.x[1], b), zb = atom_value(p.x[2], b);
+  const float ux = (xb - xa) * il, uy = (yb - ya) * il, uz = (zb - za) * il;
+
+  // moving atoms of F_k other than b, compacted into scr; their current score
+  bool mv[NSLOT], st[NSLOT];
+  int m = 0;
+  float s0 = 0.f;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int at = s * 64 + lane;
+    const bool in = at < N;
+    const bool inf = in && ((mk[s] >> k) & 1u);
+    mv[s] = inf && at != b;
+    st[s] = in && !inf && at != a;
+    const uint64_t bal = __ballot(mv[s]);
+    const int pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (mv[s]) {
+      scr[m + pre] = make_float4(p.x[0][s] - xa, p.x[1][s] - ya, p.x[2][s] - za, 0.f);
+      s0 += nearest(G, p.x[0][s], p.x[1][s], p.x[2][s]);
+    }
+    m += __popcll(bal);
+  }
+  s0 = wave_sum(s0);
+  wave_sync();
+
+  float acc[SPL];
+#pragma unroll
+  for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
+  constexpr int QG = SPL < 4 ? SPL : 4;
+  const float ih = G.inv_h;
+  const float* g0 = G.g0;
+  const int s1 = G.stride[1], s2 = G.stride[2];
+#pragma unroll
+  for (int g = 0; g < SPL; g += QG) {
+    float M[QG][9];
+#pragma unroll
+    for (int q = 0; q < QG; ++q) torsion_matrix(ux, uy, uz, sm.c[g + q], sm.s[g + q], M[q]);
+    for (int t = 0; t < m; ++t) {
+      const float4 v = scr[t];
+#pragma unroll
+      for (int q = 0; q < QG; ++q) {
+        float y0, y1, y2;
+        mat_apply(M[q], v.x, v.y, v.z, y0, y1, y2);
+        float x = xa + y0, y = ya + y1, z = za + y2;
+        int ix = clamp_node(fmaf(x - G.o[0], ih, 0.5f), G.fn[0]);
+        int iy = clamp_node(fmaf(y - G.o[1], ih, 0.5f), G.fn[1]);
+        int iz = clamp_node(fmaf(z - G.o[2], ih, 0.5f), G.fn[2]);
+        acc[g + q] += g0[ix + iy * s1 + iz * s2];
+      }
+    }
+  }
+  if (lane == 0) acc[0] = s0;
+
+  // best sample; a winner that clashes is dropped and the next best taken
+  uint32_t alive = sm.valid_a;
+  int j;
+  float Mj[9];
+  for (;;) {
+    j = wave_argmax(acc, alive);
+    if (j == 0) break;
+    torsion_matrix(ux, uy, uz, D.angles[2 * j], D.angles[2 * j + 1], Mj);
+    for (int t = lane; t < m; t += 64) {
+      const float4 v = scr[t];
+      float y0, y1, y2;
+      mat_apply(Mj, v.x, v.y, v.z, y0, y1, y2);
+      cand[t] = make_float4(xa + y0, ya + y1, za + y2, 0.f);
+    }
+    wave_sync();
+    bool clash = false;
+    for (int t = 0; t < m; ++t) {
+      const float4 c = cand[t];
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) {
+        float dx = c.x - p.x[0][s], dy = c.y - p.x[1][s], dz = c.z - p.x[2][s];
+        float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        clash |= st[s] && d2 < D.clash2;
+      }
+    }
+    if (!wave_any(clash)) break;
+    if (lane == (j & 63)) alive &= ~(1u << (j >> 6));
+    wave_sync();
+  }
+  if (j != 0) {
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      if (mv[s]) {
+        float y0, y1, y2;
+        mat_apply(Mj, p.x[0][s] - xa, p.x[1][s] - ya, p.x[2][s] - za, y0, y1, y2);
+        p.x[0][s] = xa + y0;
+        p.x[1][s] = ya + y1;
+        p.x[2][s] = za + y2;
+      }
+    }
+  }
+  wave_sync();
+  return j;
+}
+
+template <int SPL>
+__device__ void load_samples(const DockDev& D, SampleReg<SPL>& sm) {
+  const int lane = lane_id();
+  sm.valid_a = 0u;
+  sm.valid_t = 0u;
+#pragma unroll
+  for (int q = 0; q < SPL; ++q) {
+    const int j = lane + 64 * q;
+    if (j < D.A) {
+      sm.c[q] = D.angles[2 * j];
+      sm.s[q] = D.angles[2 * j + 1];
+      sm.valid_a |= 1u << q;
+    } else {
+      sm.c[q] = 1.f;
+      sm.s[q] = 0.f;
+    }
+    if (j < D.T) {
+      const int m = j < D.T / 2 ? j : j - D.T;
+      sm.d[q] = D.delta * (float)m;
+      sm.valid_t |= 1u << q;
+    } else {
+      sm.d[q] = 0.f;
+    }
+  }
+}
+
+template <int NSLOT>
+struct LigReg {
+  int N, K, abase, toff;
+  float x0[3][NSLOT];
+  uint32_t mk[NSLOT];
+  float P0[3];
+};
+
+template <int NSLOT>
+__device__ void load_ligand(const LigDev& Lg, int lig, LigReg<NSLOT>& L) {
+  const int lane = lane_id();
+  L.abase = __builtin_amdgcn_readfirstlane(Lg.atom_offset[lig]);
+  L.N = __builtin_amdgcn_readfirstlane(Lg.atom_offset[lig + 1]) - L.abase;
+  L.toff = __builtin_amdgcn_readfirstlane(Lg.tors_offset[lig]);
+  L.K = __builtin_amdgcn_readfirstlane(Lg.tors_offset[lig + 1]) - L.toff;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    const bool in = a < L.N;
+    L.x0[0][s] = in ? Lg.x[L.abase + a] : 0.f;
+    L.x0[1][s] = in ? Lg.y[L.abase + a] : 0.f;
+    L.x0[2][s] = in ? Lg.z[L.abase + a] : 0.f;
+    L.mk[s] = in ? Lg.mask[L.abase + a] : 0u;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) L.P0[c] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Lg.ref[3 * lig + c])));
+}
+
+// One restart: placement, S sweeps, final trilinear score, outputs.
+template <int NSLOT, int SPL>
+__device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& D, const SampleReg<SPL>& sm,
+                             const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand) {
+  const int lane = lane_id();
+  const int N = L.N;
+  PoseReg<NSLOT> p;
+  const float* row = D.restarts + 12 * r;
+  float m[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) m[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row[i])));
+  float q[3] = {D.c[0] + m[9], D.c[1] + m[10], D.c[2] + m[11]};
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    float vx = L.x0[0][s] - L.P0[0], vy = L.x0[1][s] - L.P0[1], vz = L.x0[2][s] - L.P0[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float y = fmaf(m[3 * c + 2], vz, fmaf(m[3 * c + 1], vy, m[3 * c] * vx));
+      p.x[c][s] = y + q[c];
+    }
+  }
+  p.piv[0] = q[0]; p.piv[1] = q[1]; p.piv[2] = q[2];
+
+  int16_t* tr = D.trace ? D.trace + ((size_t)lig * D.R + r) * (size_t)D.S * D.trace_w : nullptr;
+  for (int sw = 0; sw < D.S; ++sw) {
+    int jr0 = rot_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm);
+    int jr1 = rot_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm);
+    int jr2 = rot_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm);
+    int jt0 = trans_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm);
+    int jt1 = trans_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm);
+    int jt2 = trans_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm);
+    int16_t* trow = tr ? tr + (size_t)sw * D.trace_w : nullptr;
+    if (trow && lane == 0) {
+      trow[0] = (int16_t)jr0; trow[1] = (int16_t)jr1; trow[2] = (int16_t)jr2;
+      trow[3] = (int16_t)jt0; trow[4] = (int16_t)jt1; trow[5] = (int16_t)jt2;
+    }
+    for (int k = 0; k < L.K; ++k) {
+      int jk = tors_scan<NSLOT, SPL>(G, Lg, D, p, N, L.toff, k, L.mk, scr, cand, sm);
+      if (trow && lane == 0) trow[6 + k] = (int16_t)jk;
+    }
+  }
+
+  // final trilinear score, summed in atom order
+  float v[NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s)
+    v[s] = (s * 64 + lane < N) ? trilinear(G, p.x[0][s], p.x[1][s], p.x[2][s], nullptr) : 0.f;
+  float total = 0.f;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int cnt = min(64, N - s * 64);
+    for (int l = 0; l < cnt; ++l) total = total + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[s]), l));
+  }
+  if (lane == 0) D.final_scores[(size_t)lig * D.R + r] = total;
+  const size_t base = (size_t)L.abase * D.R + (size_t)r * N;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    if (a < N) {
+      D.wpx[base + a] = p.x[0][s];
+      D.wpy[base + a] = p.x[1][s];
+      D.wpz[base + a] = p.x[2][s];
+    }
+  }
+}
+
+// Plain method: one launch per ligand; wavefront w of the grid docks restart w.
+template <int NSLOT, int SPL>
+__global__ __launch_bounds__(256) void dock_plain_kernel(GridDev G, LigDev Lg, DockDev D, int lig) {
+  extern __shared__ float4 lds[];
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  float4* scr = lds + (size_t)wave * (2 * 64 * NSLOT);
+  float4* cand = scr + 64 * NSLOT;
+  const int r = blockIdx.x * nwaves + wave;
+  if (r >= D.R) return;
+  SampleReg<SPL> sm;
+  load_samples(D, sm);
+  LigReg<NSLOT> L;
+  load_ligand(Lg, lig, L);
+  dock_restart(G, Lg, D, sm, L, lig, r, scr, cand);
+}
+
+// Bucketed method: persistent; wavefronts pull (ligand, restart chunk) items of
+// one size bucket from an atomic cursor until the bucket is drained.
+template <int NSLOT, int SPL>
+__global__ __launch_bounds__(256) void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
+  extern __shared__ float4 lds[];
+  const int wave = threadIdx.x >> 6;
+  float4* scr = lds + (size_t)wave * (2 * 64 * NSLOT);
+  float4* cand = scr + 64 * NSLOT;
+  const int lane = lane_id();
+  const int b0 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket]);
+  const int b1 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket + 1]);
+  const int nch = (D.R + Q.chunk - 1) / Q.chunk;
+  const long long n_items = (long long)(b1 - b0) * nch;
+  if (n_items == 0) return;
+  SampleReg<SPL> sm;
+  load_samples(D, sm);
+  int cur_lig = -1;
+  LigReg<NSLOT> L;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(Q.cursor + Q.bucket, 1);
+    item = __builtin_amdgcn_readlane(item, 0);
+    if ((long long)item >= n_items) break;
+    const int li = item / nch, ch = item - li * nch;
+    const int lig = __builtin_amdgcn_readfirstlane(Q.perm[b0 + li]);
+    if (lig != cur_lig) {
+      load_ligand(Lg, lig, L);
+      cur_lig = lig;
+    }
+    const int r0 = ch * Q.chunk, r1 = min(D.R, r0 + Q.chunk);
+    for (int r = r0; r < r1; ++r) dock_restart(G, Lg, D, sm, L, lig, r, scr, cand);
+  }
+}
+
+// Per-ligand top-k over restarts (score descending, equal scores: lower r), and
+// the copy of the selected poses.  One wavefront per ligand.
+__global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, int k, float* score,
+                                                    int32_t* rid, float* ox, float* oy, float* oz,
+                                                    float* all_scores) {
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
+  const int lig = blockIdx.x * nwaves + wave;
+  if (lig >= n) return;
+  const float* fs = D.final_scores + (size_t)lig * D.R;
+  if (all_scores)
+    for (int r = lane; r < D.R; r += 64) all_scores[(size_t)lig * D.R + r] = fs[r];
+  const int abase = Lg.atom_offset[lig];
+  const int N = Lg.atom_offset[lig + 1] - abase;
+  int pk = INT_MAX, pr = -1;   // previous selection (key, r)
+  for (int qi = 0; qi < k; ++qi) {
+    int best = INT_MIN, br = INT_MAX;
+    for (int r = lane; r < D.R; r += 64) {
+      const int key = orderable(fs[r] + 0.0f);
+      const bool after = key < pk || (key == pk && r > pr);
+      if (after && (key > best || (key == best && r < br))) { best = key; br = r; }
+    }
+    const int wmax = wave_reduce_i32(best, OpMax());
+    const int rs = wave_reduce_i32(best == wmax ? br : INT_MAX, OpMin());
+    pk = wmax;
+    pr = rs;
+    if (lane == 0) {
+      score[(size_t)lig * k + qi] = fs[rs];
+      rid[(size_t)lig * k + qi] = rs;
+    }
+    const size_t src = (size_t)abase * D.R + (size_t)rs * N;
+    const size_t dst = (size_t)k * abase + (size_t)qi * N;
+    for (int a = lane; a < N; a += 64) {
+      ox[dst + a] = D.wpx[src + a];
+      oy[dst + a] = D.wpy[src + a];
+      oz[dst + a] = D.wpz[src + a];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+// LDS per block: per wavefront, scan data and torsion candidates of 64*NSLOT atoms.
+static size_t lds_bytes(int nslot, int wpb) { return (size_t)wpb * 2 * 64 * nslot * sizeof(float4); }
+
+#define LG_DISPATCH(nslot, spl, CALL)                                          \
+  switch (nslot * 100 + spl) {                                                 \
+    case 101: CALL(1, 1); case 102: CALL(1, 2); case 104: CALL(1, 4);          \
+    case 108: CALL(1, 8); case 116: CALL(1, 16);                               \
+    case 201: CALL(2, 1); case 202: CALL(2, 2); case 204: CALL(2, 4);          \
+    case 208: CALL(2, 8); case 216: CALL(2, 16);                               \
+    case 301: CALL(3, 1); case 302: CALL(3, 2); case 304: CALL(3, 4);          \
+    case 308: CALL(3, 8); case 316: CALL(3, 16);                               \
+    case 401: CALL(4, 1); case 402: CALL(4, 2); case 404: CALL(4, 4);          \
+    case 408: CALL(4, 8); case 416: CALL(4, 16);                               \
+    default: return hipErrorInvalidValue;                                      \
+  }
+
+hipError_t launch_dock_plain(int nslot, int spl, int wpb, const GridDev& G, const LigDev& Lg, const DockDev& D,
+                             int lig, hipStream_t st) {
+  const int blocks = (D.R + wpb - 1) / wpb;
+#define CALL(NS, SP)                                                                            \
+  {                                                                                             \
+    hipLaunchKernelGGL((dock_plain_kernel<NS, SP>), dim3(blocks), dim3(64 * wpb),               \
+                       lds_bytes(NS, wpb), st, G, Lg, D, lig);                              \
+    return hipGetLastError();                                                                   \
+  }
+  LG_DISPATCH(nslot, spl, CALL)
+#undef CALL
+}
+
+hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
+                              const DockDev& D, const QueueDev& Q, hipStream_t st) {
+#define CALL(NS, SP)                                                                            \
+  {                                                                                             \
+    hipLaunchKernelGGL((dock_bucket_kernel<NS, SP>), dim3(blocks), dim3(64 * wpb),              \
+                       lds_bytes(NS, wpb), st, G, Lg, D, Q);                                \
+    return hipGetLastError();                                                                   \
+  }
+  LG_DISPATCH(nslot, spl, CALL)
+#undef CALL
+}
+
+// Resident blocks per compute unit of a bucket kernel instance (the b of Eq. 1).
+hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int* blocks_per_cu) {
+#define CALL(NS, SP)                                                                                  \
+  {                                                                                                   \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_bucket_kernel<NS, SP>,    \
+                                                        64 * wpb, lds_bytes(NS, wpb));            \
+  }
+  LG_DISPATCH(nslot, spl, CALL)
+#undef CALL
+}
+
+hipError_t launch_topk(const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid, float* ox,
+                       float* oy, float* oz, float* all_scores, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int wpb = 4;
+  hipLaunchKernelGGL(topk_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), 0, st, Lg, D, n, k, score, rid, ox,
+                     oy, oz, all_scores);
+  return hipGetLastError();
+}
+
+}  // namespace lg

@@ -1,0 +1,119 @@
+// Internal device-side types and wavefront primitives of the docking library.
+// gfx950 only: 64-lane wavefronts, DPP row operations, readlane.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "lg.h"
+
+namespace lg {
+
+// Grid as the kernels see it: the library stores the pocket with a one-node
+// border of out_value on every side, so a clamp of the node index to [-1, n]
+// replaces the per-axis range test of the nearest-voxel rule.  g0 points at
+// padded node (1,1,1) = logical node (0,0,0); strides are the padded ones.
+struct GridDev {
+  const float* g0;
+  int n[3];
+  int stride[3];    // 1, nx+2, (nx+2)(ny+2)
+  float o[3];
+  float fn[3];      // (float)n per axis
+  float fn1[3];     // (float)(n-1) per axis, trilinear range
+  float inv_h;
+  float out;
+};
+
+struct LigDev {
+  const int32_t* atom_offset;
+  const int32_t* tors_offset;
+  const float* x;
+  const float* y;
+  const float* z;
+  const uint32_t* mask;
+  const int32_t* tors_atoms;
+  const float* inv_len;
+  const float* ref;
+};
+
+struct DockDev {
+  int R, A, T, S;
+  float delta, clash2;
+  float c[3];
+  const float* restarts;   // [R][12]
+  const float* angles;     // [A][2]
+  float* final_scores;     // [n*R]
+  float* wpx;              // [R*total_atoms], ligand i restart r atom a at atom_offset[i]*R + r*N + a
+  float* wpy;
+  float* wpz;
+  int16_t* trace;          // optional [n][R][S][trace_w]
+  int trace_w;
+};
+
+// Persistent work source of one bucket: items are (ligand of the bucket,
+// chunk of `chunk` restarts), pulled from `cursor` by whole wavefronts.
+struct QueueDev {
+  const int32_t* perm;          // ligand ids grouped by bucket
+  const int32_t* bucket_start;  // [B+1]
+  int32_t* cursor;              // one counter per bucket
+  int bucket;
+  int chunk;
+};
+
+// Cluster bounds of the device-side input preparation: atom cluster c holds
+// ligands with atoms <= atom[c] (first match), rotamer cluster c bonds <= rot[c].
+struct ClusterBounds {
+  int na, nr;
+  int atom[16];
+  int rot[32];
+};
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Orders a wavefront's LDS writes before its later LDS reads by other lanes:
+// waits for outstanding LDS operations and stops the compiler from moving
+// memory operations across this point.
+__device__ __forceinline__ void wave_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Row-of-16 all-reduce with DPP, then the four row results through readlane.
+// Needs all 64 lanes active.
+template <class Op>
+__device__ __forceinline__ int wave_reduce_i32(int v, Op op) {
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));   // quad_perm [1,0,3,2]
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));   // quad_perm [2,3,0,1]
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));  // row_half_mirror
+  v = op(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));  // row_mirror
+  int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return op(op(a, b), op(c, d));
+}
+
+struct OpMax { __device__ int operator()(int a, int b) const { return a > b ? a : b; } };
+struct OpMin { __device__ int operator()(int a, int b) const { return a < b ? a : b; } };
+struct OpAddF {
+  __device__ int operator()(int a, int b) const { return __float_as_int(__int_as_float(a) + __int_as_float(b)); }
+};
+
+__device__ __forceinline__ float wave_sum(float v) { return __int_as_float(wave_reduce_i32(__float_as_int(v), OpAddF())); }
+
+// Order-preserving map of a float to a signed int (total order on non-NaN).
+__device__ __forceinline__ int orderable(float f) {
+  int b = __float_as_int(f);
+  return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// Node index on the padded grid for coordinate offset f (already scaled):
+// floor of f clamped to [-1, n] -- -1 and n land on the out_value border.
+__device__ __forceinline__ int clamp_node(float f, float fn) {
+  f = __builtin_amdgcn_fmed3f(f, -1.0f, fn);
+  int i;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(f));
+  return i;
+}
+
+}  // namespace lg

@@ -1,0 +1,303 @@
+"""Thin Python binding of the docking library's C ABI (include/lg.h).
+
+Argument marshalling only: every step of the docking path runs in the HIP
+kernels of ``liblg.so``.  PyTorch provides device memory and streams.  If the
+library cannot be loaded this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblg.so")
+
+LG_OK = 0
+LG_ERR_INVALID_ARG = -1
+LG_ERR_LIMIT = -2
+LG_ERR_OUT_OF_MEMORY = -3
+LG_ERR_DEVICE = -4
+LG_ERR_UNSUPPORTED = -5
+LG_NEAREST, LG_TRILINEAR = 0, 1
+LG_PLAIN, LG_BUCKETED = 0, 1
+LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
+
+EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_set_tuning",
+           "lg_get_tuning", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters", "lg_last_error",
+           "lg_version")
+
+
+class LgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lg status {status}: {msg}")
+        self.status = status
+
+
+c_int32, c_float, c_void_p = ctypes.c_int32, ctypes.c_float, ctypes.c_void_p
+
+
+class lg_pocket_desc(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("spacing", c_float),
+                ("inv_spacing", c_float), ("origin", c_float * 3), ("center", c_float * 3),
+                ("out_value", c_float)]
+
+
+class lg_ligands(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("total_atoms", c_int32), ("total_torsions", c_int32),
+                ("atom_offset", c_void_p), ("tors_offset", c_void_p), ("x", c_void_p), ("y", c_void_p),
+                ("z", c_void_p), ("frag_mask", c_void_p), ("tors_atoms", c_void_p),
+                ("inv_bond_len", c_void_p), ("ref_point", c_void_p), ("atom_offset_host", c_void_p),
+                ("tors_offset_host", c_void_p)]
+
+
+class lg_dock_params(ctypes.Structure):
+    _fields_ = [("restarts", c_int32), ("angle_samples", c_int32), ("trans_samples", c_int32),
+                ("sweeps", c_int32), ("top_k", c_int32), ("mode", c_int32), ("trans_step", c_float),
+                ("clash_dist2", c_float), ("restart_table", c_void_p), ("angle_table", c_void_p)]
+
+
+class lg_dock_out(ctypes.Structure):
+    _fields_ = [("score", c_void_p), ("restart_id", c_void_p), ("x", c_void_p), ("y", c_void_p),
+                ("z", c_void_p), ("all_scores", c_void_p), ("trace", c_void_p), ("trace_kmax", c_int32)]
+
+
+class lg_refine_params(ctypes.Structure):
+    _fields_ = [("steps", c_int32), ("eta_t", c_float), ("eta_w", c_float), ("eta_th", c_float),
+                ("clip_t", c_float), ("clip_w", c_float), ("clip_th", c_float), ("clash_dist2", c_float)]
+
+
+class lg_tuning(ctypes.Structure):
+    _fields_ = [("n_atom_clusters", c_int32), ("atom_bounds", c_int32 * 16), ("n_rot_clusters", c_int32),
+                ("rot_bounds", c_int32 * 32), ("waves_per_block", c_int32 * 4), ("restart_chunk", c_int32),
+                ("grid_scale", c_int32), ("plain_waves_per_block", c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblg.so (building it first if it is absent).  Raises on failure."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.lg_load_pocket.argtypes = [P(lg_pocket_desc), c_void_p, c_int32, c_void_p, P(c_void_p)]
+    lib.lg_free_pocket.argtypes = [c_void_p]
+    lib.lg_dock_batch.argtypes = [c_void_p, P(lg_ligands), P(lg_dock_params), P(lg_dock_out), c_void_p]
+    lib.lg_score.argtypes = [c_void_p, P(lg_ligands), c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                             c_void_p]
+    lib.lg_refine.argtypes = [c_void_p, P(lg_ligands), P(lg_refine_params), c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p]
+    lib.lg_set_tuning.argtypes = [c_void_p, P(lg_tuning)]
+    lib.lg_get_tuning.argtypes = [c_void_p, P(lg_tuning)]
+    lib.lg_bucket_size.argtypes = [ctypes.c_int64] * 4
+    lib.lg_bucket_size.restype = ctypes.c_int64
+    lib.lg_atom_clusters.argtypes = [c_int32, c_int32, c_int32, P(c_int32)]
+    lib.lg_rotamer_clusters.argtypes = [c_int32, c_int32, P(c_int32)]
+    lib.lg_last_error.restype = ctypes.c_char_p
+    for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_set_tuning",
+                 "lg_get_tuning"):
+        getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != LG_OK:
+        raise LgError(status, _lib.lg_last_error().decode())
+
+
+# ----------------------------------------------------------------- host-only calls
+def lg_bucket_size(blocks_per_unit: int, units: int, threads_per_block: int, wave_size: int) -> int:
+    return int(load_library().lg_bucket_size(blocks_per_unit, units, threads_per_block, wave_size))
+
+
+def lg_atom_clusters(n_clusters: int, wave_size: int, max_atoms: int):
+    b = (c_int32 * max(n_clusters, 1))()
+    n = load_library().lg_atom_clusters(n_clusters, wave_size, max_atoms, b)
+    return [b[i] for i in range(n)]
+
+
+def lg_rotamer_clusters(n_clusters: int, max_rot: int):
+    b = (c_int32 * max(n_clusters, 1))()
+    n = load_library().lg_rotamer_clusters(n_clusters, max_rot, b)
+    return [b[i] for i in range(n)]
+
+
+def lg_version() -> int:
+    return int(load_library().lg_version())
+
+
+def lg_last_error() -> str:
+    return load_library().lg_last_error().decode()
+
+
+# ----------------------------------------------------------------- device data
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceLigands:
+    """A batch of ligands (or poses) in device memory, as lg_ligands expects."""
+    n: int
+    atom_offset: object
+    tors_offset: object
+    x: object
+    y: object
+    z: object
+    frag_mask: object
+    tors_atoms: object
+    inv_bond_len: object
+    ref_point: object
+    atom_offset_host: np.ndarray
+    tors_offset_host: np.ndarray
+
+    @property
+    def total_atoms(self) -> int:
+        return int(self.atom_offset_host[-1])
+
+    @property
+    def total_torsions(self) -> int:
+        return int(self.tors_offset_host[-1])
+
+    def struct(self) -> lg_ligands:
+        return lg_ligands(self.n, self.total_atoms, self.total_torsions, _ptr(self.atom_offset),
+                          _ptr(self.tors_offset), _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.frag_mask),
+                          _ptr(self.tors_atoms), _ptr(self.inv_bond_len), _ptr(self.ref_point),
+                          self.atom_offset_host.ctypes.data_as(c_void_p),
+                          self.tors_offset_host.ctypes.data_as(c_void_p))
+
+
+def device_ligands(atom_offset, tors_offset, x, y, z, frag_mask, tors_atoms, inv_bond_len, ref_point,
+                   device="cuda") -> DeviceLigands:
+    """Copy host arrays (numpy) of a ligand batch to device memory."""
+    torch = _torch()
+
+    def dev(a, dt):
+        a = np.ascontiguousarray(a, dt)
+        if a.size == 0:
+            a = np.zeros(1, dt)
+        return torch.from_numpy(a.view(np.int32) if dt == np.uint32 else a).to(device)
+
+    ao = np.ascontiguousarray(atom_offset, np.int32)
+    to = np.ascontiguousarray(tors_offset, np.int32)
+    return DeviceLigands(len(ao) - 1, dev(ao, np.int32), dev(to, np.int32), dev(x, np.float32), dev(y, np.float32),
+                         dev(z, np.float32), dev(frag_mask, np.uint32), dev(tors_atoms, np.int32),
+                         dev(inv_bond_len, np.float32), dev(ref_point, np.float32), ao, to)
+
+
+# ----------------------------------------------------------------- pocket handle
+class Pocket:
+    """lg_load_pocket / lg_free_pocket around a library-owned grid copy."""
+
+    def __init__(self, grid, origin, spacing, center, out_value=0.0, inv_spacing=None, stream=None):
+        torch = _torch()
+        lib = load_library()
+        g = grid if isinstance(grid, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(grid, np.float32))
+        g = g.contiguous()
+        nz, ny, nx = g.shape
+        inv = float(np.float32(1.0) / np.float32(spacing)) if inv_spacing is None else inv_spacing
+        self.desc = lg_pocket_desc(nx, ny, nz, float(spacing), inv, (c_float * 3)(*map(float, origin)),
+                                   (c_float * 3)(*map(float, center)), float(out_value))
+        handle = c_void_p()
+        on_dev = 1 if g.is_cuda else 0
+        _check(lib.lg_load_pocket(ctypes.byref(self.desc), c_void_p(g.data_ptr()), on_dev,
+                                  _stream_handle(stream), ctypes.byref(handle)))
+        self.handle = handle
+        self.shape = (nx, ny, nz)
+
+    def free(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            _check(_lib.lg_free_pocket(self.handle))
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def set_tuning(self, tuning: lg_tuning):
+        _check(_lib.lg_set_tuning(self.handle, ctypes.byref(tuning)))
+
+    def get_tuning(self) -> lg_tuning:
+        t = lg_tuning()
+        _check(_lib.lg_get_tuning(self.handle, ctypes.byref(t)))
+        return t
+
+
+def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_table, *, sweeps: int, top_k: int,
+                  trans_samples: int, trans_step: float, clash_dist2: float, mode: int = LG_BUCKETED,
+                  out: dict | None = None, want_all_scores=False, trace_kmax: int | None = None, stream=None):
+    """Dock a batch.  Returns a dict of device tensors: score [n,k], restart_id [n,k],
+    x/y/z [k*total_atoms], and all_scores [n,R] / trace [n,R,S,6+kmax] when asked."""
+    torch = _torch()
+    R, A = int(restart_table.shape[0]), int(angle_table.shape[0])
+    n, TA, dev = ligs.n, ligs.total_atoms, ligs.x.device
+    if out is None:
+        out = dict(score=torch.empty((n, top_k), dtype=torch.float32, device=dev),
+                   restart_id=torch.empty((n, top_k), dtype=torch.int32, device=dev),
+                   x=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
+                   y=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
+                   z=torch.empty(top_k * TA, dtype=torch.float32, device=dev))
+        if want_all_scores:
+            out["all_scores"] = torch.empty((n, R), dtype=torch.float32, device=dev)
+        if trace_kmax is not None:
+            out["trace"] = torch.full((n, R, sweeps, 6 + trace_kmax), -1, dtype=torch.int16, device=dev)
+    params = lg_dock_params(R, A, int(trans_samples), int(sweeps), int(top_k), int(mode), float(trans_step),
+                            float(clash_dist2), _ptr(restart_table), _ptr(angle_table))
+    o = lg_dock_out(_ptr(out["score"]), _ptr(out["restart_id"]), _ptr(out["x"]), _ptr(out["y"]), _ptr(out["z"]),
+                    _ptr(out.get("all_scores")), _ptr(out.get("trace")),
+                    int(trace_kmax) if out.get("trace") is not None else 0)
+    L = ligs.struct()
+    _check(_lib.lg_dock_batch(pocket.handle, ctypes.byref(L), ctypes.byref(params), ctypes.byref(o),
+                              _stream_handle(stream)))
+    return out
+
+
+def lg_score(pocket: Pocket, poses: DeviceLigands, interp: int = LG_TRILINEAR, grad: bool = False,
+             top_m: int = 0, stream=None):
+    """Score poses; returns dict(score [n], grad [6n + total_torsions] or None, top_idx, top_score)."""
+    torch = _torch()
+    dev = poses.x.device
+    n = poses.n
+    res = dict(score=torch.empty(max(n, 1), dtype=torch.float32, device=dev)[:n])
+    res["grad"] = torch.empty(max(6 * n + poses.total_torsions, 1), dtype=torch.float32, device=dev) if grad else None
+    res["top_idx"] = torch.empty(max(top_m, 1), dtype=torch.int32, device=dev)[:top_m] if top_m else None
+    res["top_score"] = torch.empty(max(top_m, 1), dtype=torch.float32, device=dev)[:top_m] if top_m else None
+    L = poses.struct()
+    _check(_lib.lg_score(pocket.handle, ctypes.byref(L), int(interp), _ptr(res["score"]), _ptr(res["grad"]),
+                         int(top_m), _ptr(res["top_idx"]), _ptr(res["top_score"]), _stream_handle(stream)))
+    return res
+
+
+def lg_refine(pocket: Pocket, poses: DeviceLigands, params: lg_refine_params, stream=None):
+    torch = _torch()
+    dev = poses.x.device
+    TA = poses.total_atoms
+    out = dict(x=torch.empty(TA, dtype=torch.float32, device=dev), y=torch.empty(TA, dtype=torch.float32, device=dev),
+               z=torch.empty(TA, dtype=torch.float32, device=dev),
+               score=torch.empty(max(poses.n, 1), dtype=torch.float32, device=dev)[:poses.n])
+    L = poses.struct()
+    _check(_lib.lg_refine(pocket.handle, ctypes.byref(L), ctypes.byref(params), _ptr(out["x"]), _ptr(out["y"]),
+                          _ptr(out["z"]), _ptr(out["score"]), _stream_handle(stream)))
+    return out

@@ -1,0 +1,179 @@
+"""GPU parity of the docking path against the CPU oracle (same seeded inputs).
+
+The bar: selected sample indices identical, final scores and poses bitwise
+identical (FP32, quantised grid), top-k identical; plain and bucketed launches
+bitwise identical; runs deterministic; batch order irrelevant.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_common import compare_ligand, dock_gpu, dock_oracle, device_pocket, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lgmod():
+    import torch
+    from paper_2303_06150_amd import lg
+    assert torch.cuda.is_available()
+    lg.load_library()
+    return lg
+
+
+def test_tiny_workload_plain_and_bucketed(lgmod, tiny):
+    lg = lgmod
+    w, pk, L = tiny["w"], tiny["pocket"], tiny["ligs"]
+    say("tiny: 64 ligands, R=32 A=64 S=2")
+    pocket = device_pocket(pk)
+    kw = dict(T=w.angle_samples, S=w.sweeps, top_k=w.top_k)
+    plain = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], mode=lg.LG_PLAIN, **kw)
+    buck = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], mode=lg.LG_BUCKETED, **kw)
+    for key in plain:
+        np.testing.assert_array_equal(plain[key], buck[key], err_msg=f"plain vs bucketed: {key}")
+    rows = np.arange(w.restarts)
+    for i in range(L.n):
+        ref = dock_oracle(pk, L, i, tiny["r32"], tiny["a32"], T=w.angle_samples, S=w.sweeps)
+        compare_ligand(buck, L, i, ref, rows, w.top_k, w.restarts, "tiny")
+    pocket.free()
+
+
+def ragged_ligands():
+    N = [1, 2, 3, 20, 63, 64, 65, 127, 128, 129, 200, 255, 256, 40]
+    K = [0, 0, 0, 5, 12, 1, 20, 32, 8, 31, 16, 32, 32, 0]
+    ids = np.arange(100, 100 + len(N))
+    return gen.ligands_from_sizes(ids, 11, np.array(N), np.array(K))
+
+
+@pytest.mark.parametrize("A,T", [(48, 40), (130, 64), (256, 256)])
+def test_ragged_sizes_and_sample_counts(lgmod, tiny, A, T):
+    lg = lgmod
+    pk = gen.pocket(48, 0.5, 60, 400, 3)
+    L = ragged_ligands()
+    assert L.n_tors.max() == 32 and L.n_atoms.max() == 256
+    r32, _ = gen.restarts(5, 5)
+    a32, _ = gen.angles(A)
+    say(f"ragged: N up to 256, K up to 32, A={A} T={T}")
+    pocket = device_pocket(pk, on_device=False)
+    kw = dict(T=T, S=1, top_k=3)
+    buck = dock_gpu(pocket, L, r32, a32, mode=lg.LG_BUCKETED, **kw)
+    plain = dock_gpu(pocket, L, r32, a32, mode=lg.LG_PLAIN, **kw)
+    for key in plain:
+        np.testing.assert_array_equal(plain[key], buck[key], err_msg=f"plain vs bucketed: {key}")
+    for i in range(L.n):
+        ref = dock_oracle(pk, L, i, r32, a32, T=T, S=1)
+        compare_ligand(buck, L, i, ref, np.arange(5), 3, 5, f"ragged A={A}")
+    pocket.free()
+
+
+def test_full_size_mixed_sampled(lgmod):
+    """Mixed workload at full per-ligand size (96^3 grid, R=256, A=T=256, S=3, top-10) in
+    the bucketed launch; sampled restarts checked against the oracle one by one."""
+    lg = lgmod
+    w = gen.WORKLOADS["mixed"]
+    ids = np.arange(0, w.n_ligands, 50)          # 2000 ligands spread over the 100k set
+    L = gen.workload_ligands(w, ids)
+    pk = gen.workload_pocket(w)
+    r32, _ = gen.restarts(w.restarts, w.seed)
+    a32, _ = gen.angles(w.angle_samples)
+    say(f"mixed slice: {L.n} ligands, {L.atom_offset[-1]} atoms")
+    pocket = device_pocket(pk)
+    out = dock_gpu(pocket, L, r32, a32, T=w.angle_samples, S=w.sweeps, top_k=w.top_k, mode=lg.LG_BUCKETED)
+    rng = np.random.default_rng(0)
+    picks = rng.choice(L.n, 6, replace=False)
+    for i in picks:
+        rows = np.sort(rng.choice(w.restarts, 3, replace=False))
+        ref = dock_oracle(pk, L, int(i), r32, a32, T=w.angle_samples, S=w.sweeps, rows=rows)
+        compare_ligand(out, L, int(i), ref, rows, w.top_k, w.restarts, "mixed")
+        say(f"  ligand {i} (N={L.n_atoms[i]}, K={L.n_tors[i]}) restarts {rows.tolist()} ok")
+    # one ligand with every restart: the top-10 selection and its poses
+    i = int(np.argmin(np.abs(L.n_atoms - 30)))
+    ref = dock_oracle(pk, L, i, r32, a32, T=w.angle_samples, S=w.sweeps)
+    compare_ligand(out, L, i, ref, np.arange(w.restarts), w.top_k, w.restarts, "mixed all restarts")
+    pocket.free()
+
+
+def test_determinism_and_batch_order(lgmod, tiny):
+    lg = lgmod
+    w, pk, L = tiny["w"], tiny["pocket"], tiny["ligs"]
+    pocket = device_pocket(pk)
+    kw = dict(T=w.angle_samples, S=w.sweeps, top_k=4, mode=lg.LG_BUCKETED)
+    a = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], **kw)
+    b = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], **kw)
+    for key in a:
+        np.testing.assert_array_equal(a[key], b[key])
+    perm = np.random.default_rng(1).permutation(L.n)
+    Lp = L.subset(perm)
+    c = dock_gpu(pocket, Lp, tiny["r32"], tiny["a32"], **kw)
+    np.testing.assert_array_equal(c["all_scores"], a["all_scores"][perm])
+    np.testing.assert_array_equal(c["restart_id"], a["restart_id"][perm])
+    np.testing.assert_array_equal(c["trace"][..., :12], a["trace"][perm][..., :12])
+    pocket.free()
+
+
+def test_score_and_gradient(lgmod, tiny):
+    lg = lgmod
+    import torch
+    pk, L = tiny["pocket"], tiny["ligs"]
+    pocket = device_pocket(pk)
+    rng = np.random.default_rng(3)
+    # poses: input conformations moved into the pocket with random offsets
+    shift = pk.center + rng.uniform(-3, 3, size=(L.n, 3)).astype(np.float32)
+    lig_of = np.repeat(np.arange(L.n), L.n_atoms)
+    cen = np.stack([L.ref_point[0::3], L.ref_point[1::3], L.ref_point[2::3]], 1)
+    xs = (L.x - cen[lig_of, 0] + shift[lig_of, 0]).astype(np.float32)
+    ys = (L.y - cen[lig_of, 1] + shift[lig_of, 1]).astype(np.float32)
+    zs = (L.z - cen[lig_of, 2] + shift[lig_of, 2]).astype(np.float32)
+    refp = shift.reshape(-1).astype(np.float32)
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, xs, ys, zs, L.frag_mask, L.tors_atoms,
+                           L.inv_bond_len, refp)
+    near = lg.lg_score(pocket, dl, lg.LG_NEAREST)["score"].cpu().numpy()
+    tri = lg.lg_score(pocket, dl, lg.LG_TRILINEAR, grad=True, top_m=10)
+    torch.cuda.synchronize()
+    ts, tg = tri["score"].cpu().numpy(), tri["grad"].cpu().numpy()
+    worst = 0.0
+    for i in range(L.n):
+        a0, a1 = L.atom_offset[i], L.atom_offset[i + 1]
+        xyz = np.stack([xs[a0:a1], ys[a0:a1], zs[a0:a1]], 1).astype(np.float64)
+        assert near[i] == oracle.score(pk, xyz, 0, 32)
+        assert ts[i] == oracle.score(pk, xyz, 1, 32)
+        lig = L.ligand(i)
+        _, g64 = oracle.pose_grad(lig, pk, xyz, shift[i].astype(np.float64))
+        K = int(L.n_tors[i])
+        g = tg[6 * i + L.tors_offset[i]: 6 * i + L.tors_offset[i] + 6 + K]
+        scale = max(np.abs(g64).max(), 1e-3)
+        worst = max(worst, np.abs(g - g64).max() / scale)
+    assert worst < 1e-4, worst
+    order = np.lexsort((np.arange(L.n), -ts.astype(np.float64)))[:10]
+    np.testing.assert_array_equal(tri["top_idx"].cpu().numpy(), order)
+    np.testing.assert_array_equal(tri["top_score"].cpu().numpy(), ts[order])
+    pocket.free()
+
+
+def test_device_validation_errors(lgmod, tiny):
+    lg = lgmod
+    import torch
+    pk, L = tiny["pocket"], tiny["ligs"]
+    pocket = device_pocket(pk)
+    r = torch.from_numpy(tiny["r32"]).cuda()
+    a = torch.from_numpy(tiny["a32"]).cuda()
+    bad = L.tors_atoms.copy()
+    bad[1] = 999                                   # moving-side atom out of range
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, bad, L.inv_bond_len,
+                           L.ref_point)
+    with pytest.raises(lg.LgError) as e:
+        lg.lg_dock_batch(pocket, dl, r, a, sweeps=1, top_k=1, trans_samples=64, trans_step=0.0625,
+                         clash_dist2=oracle.CLASH2)
+    assert e.value.status == lg.LG_ERR_INVALID_ARG
+    with pytest.raises(lg.LgError) as e:
+        lg.lg_dock_batch(pocket, device_ligands_ok(lg, L), r, a, sweeps=1, top_k=33, trans_samples=64,
+                         trans_step=0.0625, clash_dist2=oracle.CLASH2)
+    assert e.value.status == lg.LG_ERR_INVALID_ARG
+    pocket.free()
+
+
+def device_ligands_ok(lg, L):
+    return lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                             L.inv_bond_len, L.ref_point)
