@@ -53,12 +53,12 @@ enum { LG_PLAIN = 0, LG_BUCKETED = 1 };
 
 /* Docking site (Sec. 2): a node-centred grid of float32 values, x fastest,
  * node (ix,iy,iz) at origin + (ix,iy,iz)*spacing.  Nearest lookups take node
- * (int)f per axis with f = fma(x - origin, inv_spacing, 0.5) when 0 <= f < n on
- * every axis; trilinear lookups need 0 <= (x - origin)*inv_spacing < n-1 on every
- * axis.  Positions outside either rule score out_value (zero gradient).
+ * (int)f per axis with f = fma(x, inv_spacing, c), c = fma(-origin,
+ * inv_spacing, 0.5) (FP32), when 0 <= f < n on every axis; trilinear lookups
+ * need 0 <= (x - origin)*inv_spacing < n-1 on every axis.  Positions outside either rule score out_value (zero gradient).
  * Restart offsets are relative to `center`. */
 typedef struct {
-  int32_t nx, ny, nz;        /* 2..1024 each */
+  int32_t nx, ny, nz;        /* 2..1024 each; (nx+2)(ny+2) < 2^21 and (nx+2)(ny+2)(nz+2) < 2^29 */
   float spacing;             /* Angstrom, > 0 */
   float inv_spacing;         /* the FP32 value of 1/spacing every lookup uses */
   float origin[3];
@@ -196,7 +196,7 @@ lg_status lg_refine(lg_pocket pocket, const lg_ligands* poses, const lg_refine_p
  * by the kernel instance for ceil(atom bound / 64) atom slots per lane, with
  * waves_per_block[slots-1] wavefronts per block; its persistent grid is
  * grid_scale times the resident blocks of Eq. 1.  Work items are chunks of
- * restart_chunk restarts of one ligand. */
+ * restart_chunk restarts of one ligand.  Results do not depend on the tuning. */
 typedef struct {
   int32_t n_atom_clusters;        /* 1..16 */
   int32_t atom_bounds[16];        /* increasing, each 1..LG_MAX_ATOMS */
@@ -206,10 +206,36 @@ typedef struct {
   int32_t restart_chunk;          /* >= 1 */
   int32_t grid_scale;             /* 1..64 */
   int32_t plain_waves_per_block;  /* 1, 2 or 4 */
+  int32_t use_graph;              /* 1: capture once and replay as a HIP graph; 0: launch
+                                     directly on the caller's stream with timing events
+                                     between the bucket launches */
 } lg_tuning;
 
 lg_status lg_set_tuning(lg_pocket pocket, const lg_tuning* tuning);
 lg_status lg_get_tuning(lg_pocket pocket, lg_tuning* tuning);
+
+/* Per-bucket report of the last LG_BUCKETED call on a handle -- the MI355X
+ * analog of the paper's Table 1 (registers and resident blocks per size class)
+ * plus the launch duration, measured with events recorded in the graph around
+ * each bucket's launch.  Fills up to `capacity` entries (NULL: none) and returns
+ * the number of bucket launches, or a negative lg_status.  Synchronises the
+ * device to read ligand counts and durations. */
+typedef struct {
+  int32_t bucket;            /* atom cluster * n_rot_clusters + rotamer cluster */
+  int32_t atom_bound;        /* atoms <= atom_bound */
+  int32_t rot_bound;         /* bonds <= rot_bound */
+  int32_t slots;             /* atom slots per lane of the kernel instance */
+  int32_t samples_per_lane;
+  int32_t waves_per_block;
+  int32_t vgprs;             /* architected VGPRs per lane of the instance */
+  int32_t lds_bytes;         /* LDS per block */
+  int32_t blocks_per_cu;     /* b of Eq. 1 */
+  int32_t blocks;            /* persistent grid of the launch */
+  int32_t ligands;           /* ligands in the bucket */
+  float ms;                  /* launch duration, -1 if unknown */
+} lg_bucket_stat;
+
+int32_t lg_bucket_stats(lg_pocket pocket, lg_bucket_stat* out, int32_t capacity);
 
 /* Eq. 1 of the paper: ligands per bucket l = b * units * t / ws, with b the
  * resident blocks per compute unit of the class kernel, units the compute

@@ -65,10 +65,14 @@ template <class R>
 struct Grid {
   int n[3];
   R o[3], h, inv_h, out;
+  R c0[3];    // offset of the nearest-node map: c0 = fma(-o, 1/h, 1/2)
   const float* v;
   explicit Grid(const og_grid* g) : h((R)g->spacing), inv_h((R)g->inv_spacing), out((R)g->out_value), v(g->values) {
     n[0] = g->nx; n[1] = g->ny; n[2] = g->nz;
-    for (int a = 0; a < 3; ++a) o[a] = (R)g->origin[a];
+    for (int a = 0; a < 3; ++a) {
+      o[a] = (R)g->origin[a];
+      c0[a] = std::fma(-o[a], inv_h, (R)0.5);
+    }
   }
   R at(int ix, int iy, int iz) const { return (R)v[((size_t)iz * n[1] + iy) * n[0] + ix]; }
 };
@@ -102,15 +106,16 @@ struct Pose {
 
 using std::fma;
 
-// ---- nearest-voxel lookup: per axis f = fma(x - o, 1/h, 1/2); the atom is in
-// the grid iff 0 <= f < n on every axis, then the node is (int)f; otherwise it
-// contributes the far-field value.
+// ---- nearest-voxel lookup: the nearest node of coordinate x is round((x - o)/h),
+// evaluated per axis as the affine map f = fma(x, 1/h, c0) with
+// c0 = fma(-o, 1/h, 1/2); the atom is in the grid iff 0 <= f < n on every axis,
+// then the node is (int)f; otherwise it contributes the far-field value.
 template <class R>
 R nearest(const Grid<R>& g, R x, R y, R z) {
   R c[3] = {x, y, z};
   int i[3];
   for (int a = 0; a < 3; ++a) {
-    R f = fma(c[a] - g.o[a], g.inv_h, (R)0.5);
+    R f = fma(c[a], g.inv_h, g.c0[a]);
     if (!(f >= (R)0 && f < (R)g.n[a])) return g.out;
     i[a] = (int)f;
   }
