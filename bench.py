@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Benchmark: ligands docked per second at 256 restarts on one MI355X.
+
+Workload (default): the mixed library -- 100,000 ligands, atoms lognormal
+(median 38, clipped to [12, 120]), rotatable bonds round(0.18 N + N(0, 2))
+clipped to [0, 24]; 96^3 pocket grid at 0.375 A; 256 restarts, 256 angle and
+256 translation samples, 3 sweeps, top-10 per ligand.  Synthetic, seeded inputs
+(the paper's ligand library is not public), resident in device memory before
+the timed region.
+
+A step is one lg_dock_batch call over the whole library in the bucketed
+persistent mode (device-side bucketing, one persistent launch per size bucket,
+replayed as one HIP graph, per-ligand top-k).  The plain method (one launch
+per ligand, largest-class kernel) is timed on a prefix of the same library and
+reported beside it, with the single-bucket ablation.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: non-packed VALU issue, lane-ops/s
+
+# Algorithmic VALU lane-operations of the method, per unit of work (the op script
+# of the kernels: transform, nearest-voxel index, accumulate):
+OPS_ROT = 17      # per (rotation sample, atom)
+OPS_TRANS = 7     # per (translation sample, atom)
+OPS_TORS = 27     # per (torsion sample, moving atom)
+OPS_TMAT = 16     # per torsion sample: rotation matrix about the bond
+OPS_PAIR = 8      # per (moving, static) pair of the selected torsion sample
+OPS_PLACE = 15    # per atom per restart: placement
+OPS_TRI = 45      # per atom per restart: trilinear final score
+
+
+def algorithmic_ops(n_atoms, frag_sizes_per_lig, R, A, T, S):
+    """Lane-ops of docking each ligand (array over ligands).
+
+    frag_sizes_per_lig: list of arrays |F_k| per ligand."""
+    ops = np.zeros(len(n_atoms))
+    for i, (N, F) in enumerate(zip(n_atoms, frag_sizes_per_lig)):
+        N = float(N)
+        mv = np.asarray(F, np.float64) - 1.0                 # moving atoms excluding the axis atom
+        per_sweep = (3 * A * N * OPS_ROT + 3 * T * N * OPS_TRANS + A * mv.sum() * OPS_TORS
+                     + len(F) * A * OPS_TMAT + (mv * (N - mv - 2)).sum() * OPS_PAIR)
+        ops[i] = R * (S * per_sweep + N * (OPS_PLACE + OPS_TRI))
+    return ops
+
+
+def frag_sizes(L):
+    out = []
+    for i in range(L.n):
+        a0, a1 = L.atom_offset[i], L.atom_offset[i + 1]
+        m = L.frag_mask[a0:a1]
+        K = int(L.n_tors[i])
+        out.append([int(((m >> k) & 1).sum()) for k in range(K)])
+    return out
+
+
+def bucket_of(n_atoms, n_tors, tuning):
+    na, nr = tuning.n_atom_clusters, tuning.n_rot_clusters
+    ab = list(tuning.atom_bounds[:na])
+    ab[-1] = 256
+    rb = list(tuning.rot_bounds[:nr])
+    ca = np.full(len(n_atoms), na - 1)
+    for c in range(na - 1, -1, -1):
+        ca = np.where(n_atoms <= ab[c], c, ca)
+    cr = np.full(len(n_tors), nr - 1)
+    for c in range(nr - 1, -1, -1):
+        cr = np.where(n_tors <= rb[c], c, cr)
+    return ca * nr + cr
+
+
+def read_traffic(kernel_tag):
+    """HBM traffic per dispatch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("dock.hip", "lg_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2303_06150_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(w, sample_ids, procs):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    chunks = [c for c in np.array_split(np.asarray(sample_ids), procs) if len(c)]
+    t0 = time.perf_counter()
+    with ctx.Pool(len(chunks)) as pool:
+        done = pool.map(_oracle_chunk, [(w.name, [int(i) for i in c]) for c in chunks])
+    wall = time.perf_counter() - t0
+    return sum(done), wall, len(chunks)
+
+
+def _oracle_chunk(arg):
+    name, ids = arg
+    sys.path.insert(0, ROOT)
+    import gen
+    import oracle
+    w = gen.WORKLOADS[name]
+    pk = gen.workload_pocket(w)
+    L = gen.workload_ligands(w, np.array(ids, np.int64))
+    r32, _ = gen.restarts(w.restarts, w.seed)
+    a32, _ = gen.angles(w.angle_samples)
+    for i in range(L.n):
+        oracle.dock_ligand(L.ligand(i), pk, r32.astype(np.float64), a32.astype(np.float64), w.angle_samples,
+                           w.sweeps, oracle.trans_step(w.angle_samples), oracle.CLASH2, bits=32,
+                           want_poses=False, want_trace=False)
+    return L.n
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mixed")
+    ap.add_argument("--ligands", type=int, default=None, help="use the first n ligands of the workload")
+    ap.add_argument("--plain-ligands", type=int, default=2000)
+    ap.add_argument("--ablation-ligands", type=int, default=20000)
+    ap.add_argument("--cpu-sample", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side-runs", action="store_true", help="skip the plain and ablation runs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build docks on one GPU; --gpus {args.gpus} is not supported "
+              "(ligands shard across GPUs with no exchange but the final ranking).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gen
+    from paper_2303_06150_amd import lg
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    w = gen.WORKLOADS[args.workload]
+    n = w.n_ligands if args.ligands is None else min(args.ligands, w.n_ligands)
+    t0 = time.perf_counter()
+    L = gen.workload_ligands(w, np.arange(n, dtype=np.int64))
+    pk = gen.workload_pocket(w)
+    r32, _ = gen.restarts(w.restarts, w.seed)
+    a32, _ = gen.angles(w.angle_samples)
+    log(f"inputs: {n} ligands, {int(L.atom_offset[-1])} atoms, {int(L.tors_offset[-1])} bonds "
+        f"({time.perf_counter() - t0:.1f}s)")
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    lg.load_library()
+    pocket = lg.Pocket(torch.from_numpy(pk.grid).to(dev), pk.origin, pk.spacing, pk.center, pk.out_value,
+                       inv_spacing=pk.inv_spacing)
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                           L.inv_bond_len, L.ref_point)
+    rt = torch.from_numpy(r32).to(dev)
+    at = torch.from_numpy(a32).to(dev)
+    T = w.angle_samples
+    step = float(np.float32(4.0 / T))
+    clash2 = float(np.float32(4.84))
+    kw = dict(sweeps=w.sweeps, top_k=w.top_k, trans_samples=T, trans_step=step, clash_dist2=clash2)
+
+    def dock(ligs, mode, out=None):
+        return lg.lg_dock_batch(pocket, ligs, rt, at, mode=mode, out=out, **kw)
+
+    # ---- bucketed persistent path: the timed steps
+    out = None
+    for s in range(args.warmup):
+        out = dock(dl, lg.LG_BUCKETED, out)
+        torch.cuda.synchronize()
+        log(f"warmup step {s} done")
+    bucket_ms = {}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        out = dock(dl, lg.LG_BUCKETED, out)
+        log(f"step {s} enqueued")
+    torch.cuda.synchronize()
+    log("timed steps done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
+    value = n * args.steps / elapsed
+
+    # ---- per-kernel durations: one more step launched directly on the stream (no
+    # graph), with HIP events recorded on that stream between the bucket launches
+    tuning = pocket.get_tuning()
+    eager = lg.lg_tuning.from_buffer_copy(tuning)
+    eager.use_graph = 0
+    pocket.set_tuning(eager)
+    out = dock(dl, lg.LG_BUCKETED, out)
+    torch.cuda.synchronize()
+    stats = pocket.bucket_stats()
+    for b in stats:
+        bucket_ms.setdefault(b["bucket"], []).append(b["ms"])
+    pocket.set_tuning(tuning)
+    log("timing step (events between bucket launches) done")
+
+    # ---- roofline of the dominant kernel (the bucket launch with the most time)
+    bid = bucket_of(L.n_atoms, L.n_tors, tuning)
+    fs = frag_sizes(L)
+    ops = algorithmic_ops(L.n_atoms, fs, w.restarts, w.angle_samples, T, w.sweeps)
+    dom = max(stats, key=lambda b: np.mean(bucket_ms.get(b["bucket"], [0])))
+    dom_ms = float(np.mean(bucket_ms[dom["bucket"]]))
+    dom_ops = float(ops[bid == dom["bucket"]].sum())
+    achieved = dom_ops / (dom_ms * 1e-3)
+    kernel_tag = f"dock_bucket_s{dom['slots']}_spl{dom['samples_per_lane']}_{args.workload}"
+    traffic = read_traffic(kernel_tag)
+    roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(PEAK_LANE_OPS / 1e12, 3),
+                    unit="TOP/s", frac=round(achieved / PEAK_LANE_OPS, 4), traffic=traffic,
+                    kernel=f"dock_bucket_kernel<{dom['slots']},{dom['samples_per_lane']}>",
+                    kernel_ms=round(dom_ms, 3), ligands_in_launch=int(dom["ligands"]),
+                    algorithmic_ops_per_launch=dom_ops)
+    total_ops = float(ops.sum())
+
+    # ---- side runs: plain per-ligand launches, single-bucket ablation
+    side = {}
+    if not args.no_side_runs:
+        npl = min(args.plain_ligands, n)
+        Lp = L.subset(np.arange(npl))
+        dlp = lg.device_ligands(Lp.atom_offset, Lp.tors_offset, Lp.x, Lp.y, Lp.z, Lp.frag_mask, Lp.tors_atoms,
+                                Lp.inv_bond_len, Lp.ref_point)
+        Lw = L.subset(np.arange(min(8, n)))
+        dock(lg.device_ligands(Lw.atom_offset, Lw.tors_offset, Lw.x, Lw.y, Lw.z, Lw.frag_mask, Lw.tors_atoms,
+                               Lw.inv_bond_len, Lw.ref_point), lg.LG_PLAIN)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        dock(dlp, lg.LG_PLAIN)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - tp
+        ob = dock(dlp, lg.LG_BUCKETED)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        dock(dlp, lg.LG_BUCKETED, ob)
+        torch.cuda.synchronize()
+        buck_small_s = time.perf_counter() - tb
+        side["plain"] = dict(ligands=npl, value=round(npl / plain_s, 2), unit="ligands/s")
+        side["bucketed_same_prefix"] = dict(ligands=npl, value=round(npl / buck_small_s, 2), unit="ligands/s")
+        log(f"plain: {npl / plain_s:.1f} ligands/s on {npl} ligands; bucketed on the same: {npl / buck_small_s:.1f}")
+        # ablation: one bucket for every ligand (the 1x1-cluster baseline), largest-class kernel
+        nab = min(args.ablation_ligands, n)
+        La = L.subset(np.arange(nab))
+        dla = lg.device_ligands(La.atom_offset, La.tors_offset, La.x, La.y, La.z, La.frag_mask, La.tors_atoms,
+                                La.inv_bond_len, La.ref_point)
+        one = lg.lg_tuning.from_buffer_copy(tuning)
+        one.n_atom_clusters = 1
+        one.atom_bounds[0] = 256
+        one.n_rot_clusters = 1
+        one.rot_bounds[0] = 32
+        pocket.set_tuning(one)
+        oa = dock(dla, lg.LG_BUCKETED)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        dock(dla, lg.LG_BUCKETED, oa)
+        torch.cuda.synchronize()
+        abl_s = time.perf_counter() - ta
+        pocket.set_tuning(tuning)
+        ob = dock(dla, lg.LG_BUCKETED)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        dock(dla, lg.LG_BUCKETED, ob)
+        torch.cuda.synchronize()
+        buck_ab_s = time.perf_counter() - tb
+        side["one_bucket_ablation"] = dict(ligands=nab, value=round(nab / abl_s, 2), unit="ligands/s",
+                                           bucketed_same_ligands=round(nab / buck_ab_s, 2))
+        log(f"one-bucket ablation: {nab / abl_s:.1f} ligands/s vs bucketed {nab / buck_ab_s:.1f} on {nab}")
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        procs = max(1, min(16, os.cpu_count() or 1))
+        sample = np.linspace(0, w.n_ligands - 1, args.cpu_sample).astype(np.int64)
+        done, wall, used = cpu_baseline(w, sample, procs)
+        cpu = dict(value=round(done / wall, 3), unit="ligands/s", cores=used, kind="oracle",
+                   sample=f"{done} ligands of the {args.workload} workload (ids spread evenly over "
+                          f"{w.n_ligands}), every restart ({w.restarts}), FP32 oracle, one process per core")
+        log(f"cpu baseline: {done / wall:.2f} ligands/s on {used} processes")
+
+    buckets = [dict(bucket=b["bucket"], atoms_le=b["atom_bound"], slots=b["slots"], vgprs=b["vgprs"],
+                    lds_bytes=b["lds_bytes"], blocks_per_cu=b["blocks_per_cu"], waves_in_flight=b["blocks"] * b["waves_per_block"],
+                    ligands=b["ligands"], ms=round(float(np.mean(bucket_ms.get(b["bucket"], [b["ms"]]))), 3))
+               for b in stats]
+    rec = dict(
+        metric="ligands docked/sec at 256 restarts (bucketed vs plain, 1 MI355X)",
+        value=round(value, 2), unit="ligands/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms_per_step, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32", data="synthetic",
+        config=dict(workload=f"{args.workload}: {n} ligands, atoms {w.nlo}-{w.nhi} (lognormal median 38), "
+                             f"bonds {w.klo}-{w.khi}, {w.grid_n}^3 grid @ {w.spacing} A, R={w.restarts}, "
+                             f"A=T={w.angle_samples}, S={w.sweeps}, top-{w.top_k}",
+                    ligands=n, restarts=w.restarts, angle_samples=w.angle_samples, sweeps=w.sweeps,
+                    top_k=w.top_k, mode="bucketed persistent, one HIP graph"),
+        roofline=roofline, cpu_baseline=cpu,
+        algorithmic_top_s_whole_step=round(total_ops / (ms_per_step * 1e-3) / 1e12, 3),
+        speedup_vs_plain=round(value / side["plain"]["value"], 2) if "plain" in side else None,
+        buckets=buckets, **side)
+    print(json.dumps(rec), flush=True)
+    pocket.free()
+
+
+if __name__ == "__main__":
+    main()

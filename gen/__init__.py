@@ -15,6 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -177,10 +178,19 @@ def ligands_from_sizes(ids, seed: int, n_req, k_req) -> Ligands:
     ta = np.zeros(max(TB, 1), np.int32)
     tb = np.zeros(max(TB, 1), np.int32)
     kout = np.empty(cnt, np.int32)
-    rc = lib.gen_ligands(ctypes.c_int(cnt), _p(ids), ctypes.c_uint64(seed), _p(n_req), _p(k_req),
-                         _p(ao64), _p(bo64), _p(xyz64), _p(parent), _p(mask), _p(ta), _p(tb), _p(kout))
-    if rc != 0:
-        raise RuntimeError(f"gen_ligands failed ({rc})")
+
+    def run(lo, hi):
+        # offsets are absolute, so every chunk writes into the shared output arrays
+        return lib.gen_ligands(ctypes.c_int(hi - lo), _p(ids[lo:hi]), ctypes.c_uint64(seed), _p(n_req[lo:hi]),
+                               _p(k_req[lo:hi]), _p(ao64[lo:hi]), _p(bo64[lo:hi]), _p(xyz64), _p(parent), _p(mask),
+                               _p(ta), _p(tb), _p(kout[lo:hi]))
+
+    nthreads = max(1, min(16, os.cpu_count() or 1, cnt // 256))
+    bounds = np.linspace(0, cnt, nthreads + 1).astype(int)
+    with ThreadPoolExecutor(nthreads) as ex:
+        rcs = list(ex.map(lambda b: run(b[0], b[1]), zip(bounds[:-1], bounds[1:])))
+    if any(rc != 0 for rc in rcs):
+        raise RuntimeError(f"gen_ligands failed ({rcs})")
     # compact bonds to the realised counts
     keep = np.zeros(max(TB, 1), bool)
     for_idx = np.repeat(np.arange(cnt), k_req)

@@ -209,6 +209,9 @@ typedef struct {
   int32_t use_graph;              /* 1: capture once and replay as a HIP graph; 0: launch
                                      directly on the caller's stream with timing events
                                      between the bucket launches */
+  int32_t lazy_clash;             /* 0: decide every torsion sample's clash test in the
+                                     scoring pass (pruned pair list); 1: test only the
+                                     winner and drop it while it clashes */
 } lg_tuning;
 
 lg_status lg_set_tuning(lg_pocket pocket, const lg_tuning* tuning);

@@ -20,13 +20,16 @@ hipError_t launch_dock_plain(int nslot, int spl, int wpb, const GridDev& G, cons
                              int lig, hipStream_t st);
 hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
                               const DockDev& D, const QueueDev& Q, hipStream_t st);
-hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int* blocks_per_cu);
+hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int tab_len, int* blocks_per_cu);
+hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr);
 hipError_t launch_topk(const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid, float* ox,
                        float* oy, float* oz, float* all_scores, hipStream_t st);
 hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, float* score, float* grad,
                         hipStream_t st);
 hipError_t launch_rank_prep(const float* score, int n, float* keys, int32_t* vals, hipStream_t st);
 hipError_t launch_pad(const float* src, int nx, int ny, int nz, float out, float* dst, hipStream_t st);
+hipError_t launch_brick(const float* padded, int px, int py, int pz, int nbx, int nby, int nbz, float out,
+                        float* brick, hipStream_t st);
 hipError_t launch_bucketing(const int32_t* atom_offset, const int32_t* tors_offset, int n, const ClusterBounds& cb,
                             int32_t* cls, int32_t* counts, int32_t* start, int32_t* fill, int32_t* perm,
                             int32_t* cursors, hipStream_t st);
@@ -77,6 +80,8 @@ lg_tuning default_tuning() {
   t.restart_chunk = 8;
   t.grid_scale = 1;
   t.plain_waves_per_block = 4;
+  t.use_graph = 1;
+  t.lazy_clash = 0;
   return t;
 }
 
@@ -94,6 +99,7 @@ struct lg_pocket_s {
   int cus = 0;
   lg_pocket_desc desc{};
   float* padded = nullptr;
+  float* brick = nullptr;
   lg::GridDev grid{};
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -101,6 +107,11 @@ struct lg_pocket_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gkey;
   hipStream_t capture = nullptr;   // graphs are captured here, then launched on the caller's stream
+  // per-bucket launches of the captured graph and the events around them
+  std::vector<lg_bucket_stat> launches;
+  std::vector<hipEvent_t> events;
+  int32_t* counts_dev = nullptr;
+  bool timed = false;
 };
 
 namespace {
@@ -230,6 +241,11 @@ lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t 
   *out = nullptr;
   if (desc->nx < 2 || desc->ny < 2 || desc->nz < 2 || desc->nx > 1024 || desc->ny > 1024 || desc->nz > 1024)
     return fail(LG_ERR_LIMIT, "grid dims %d x %d x %d outside 2..1024", desc->nx, desc->ny, desc->nz);
+  // byte offsets into the padded grid are 32-bit and plane strides 24-bit signed
+  if (4LL * (desc->nx + 2) * (desc->ny + 2) >= (1LL << 23) ||
+      128LL * ((desc->nx + 5) / 4) * ((desc->ny + 5) / 4) * ((desc->nz + 3) / 2) >= (1LL << 31))
+    return fail(LG_ERR_LIMIT, "grid %d x %d x %d too large (padded plane < 2^21 nodes, volume < 2^29 nodes)",
+                desc->nx, desc->ny, desc->nz);
   if (!(desc->spacing > 0.f) || !(desc->inv_spacing > 0.f) || !std::isfinite(desc->spacing))
     return fail(LG_ERR_INVALID_ARG, "spacing must be positive");
   int dev = 0;
@@ -265,9 +281,19 @@ lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t 
         hipStreamSynchronize(st) != hipSuccess)
       s = fail(LG_ERR_DEVICE, "grid upload failed");
   }
+  const int nbx = (nx + 2 + 3) / 4, nby = (ny + 2 + 3) / 4, nbz = (nz + 2 + 1) / 2;
+  const size_t nbrick = (size_t)nbx * nby * nbz * 32;
+  if (s == LG_OK && hipMalloc(&p->brick, nbrick * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    p->brick = nullptr;
+    s = fail(LG_ERR_OUT_OF_MEMORY, "brick grid allocation failed");
+  }
+  if (s == LG_OK && lg::launch_brick(p->padded, nx + 2, ny + 2, nz + 2, nbx, nby, nbz, desc->out_value, p->brick, st) != hipSuccess)
+    s = fail(LG_ERR_DEVICE, "brick kernel launch failed");
   if (s == LG_OK && hipStreamSynchronize(st) != hipSuccess) s = fail(LG_ERR_DEVICE, "stream synchronise failed");
   if (s != LG_OK) {
     (void)hipFree(p->padded);
+    if (p->brick) (void)hipFree(p->brick);
     delete p;
     return s;
   }
@@ -276,6 +302,9 @@ lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t 
   G.stride[1] = nx + 2;
   G.stride[2] = (nx + 2) * (ny + 2);
   G.g0 = p->padded + 1 + G.stride[1] + G.stride[2];
+  G.gb = reinterpret_cast<const char*>(p->padded);
+  for (int a = 0; a < 3; ++a) G.bs[a] = 4 * G.stride[a];
+  G.b0 = 4 * (1 + G.stride[1] + G.stride[2]);
   G.n[0] = nx; G.n[1] = ny; G.n[2] = nz;
   for (int a = 0; a < 3; ++a) {
     G.o[a] = desc->origin[a];
@@ -284,6 +313,13 @@ lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t 
   }
   G.inv_h = desc->inv_spacing;
   G.out = desc->out_value;
+  for (int a = 0; a < 3; ++a) G.c0[a] = std::fma(-desc->origin[a], desc->inv_spacing, 0.5f);
+  G.gk = reinterpret_cast<const char*>(p->brick);
+  G.nb[0] = nbx; G.nb[1] = nby; G.nb[2] = nbz;
+  G.tab_base[0] = 0;
+  G.tab_base[1] = nx + 2;
+  G.tab_base[2] = (nx + 2) + (ny + 2);
+  G.tab_len = (nx + 2) + (ny + 2) + (nz + 2);
   if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
     (void)hipFree(p->padded);
     delete p;
@@ -298,8 +334,10 @@ lg_status lg_free_pocket(lg_pocket p) {
   (void)hipDeviceSynchronize();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->capture) (void)hipStreamDestroy(p->capture);
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   if (p->ws) (void)hipFree(p->ws);
   if (p->padded) (void)hipFree(p->padded);
+  if (p->brick) (void)hipFree(p->brick);
   delete p;
   return LG_OK;
 }
@@ -321,6 +359,8 @@ lg_status lg_set_tuning(lg_pocket p, const lg_tuning* t) {
     return fail(LG_ERR_INVALID_ARG, "plain_waves_per_block must be 1, 2 or 4");
   if (t->restart_chunk < 1 || t->grid_scale < 1 || t->grid_scale > 64)
     return fail(LG_ERR_INVALID_ARG, "restart_chunk >= 1 and grid_scale in 1..64");
+  if (t->use_graph != 0 && t->use_graph != 1) return fail(LG_ERR_INVALID_ARG, "use_graph must be 0 or 1");
+  if (t->lazy_clash != 0 && t->lazy_clash != 1) return fail(LG_ERR_INVALID_ARG, "lazy_clash must be 0 or 1");
   p->tuning = *t;
   if (p->gexec) {
     (void)hipGraphExecDestroy(p->gexec);
@@ -383,6 +423,8 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   D.S = P->sweeps;
   D.delta = P->trans_step;
   D.clash2 = P->clash_dist2;
+  // 0.05 A margin of the risky-pair bound (the FP32 rotation stays within ~1e-5 A of the circle)
+  D.clash_r2 = P->clash_dist2 > 0.f ? (std::sqrt(P->clash_dist2) + 0.05f) * (std::sqrt(P->clash_dist2) + 0.05f) : 0.f;
   for (int a = 0; a < 3; ++a) D.c[a] = p->desc.center[a];
   D.restarts = P->restart_table;
   D.angles = P->angle_table;
@@ -390,6 +432,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   D.wpx = (float*)(ws + o_wp);
   D.wpy = D.wpx + (size_t)R * L->total_atoms;
   D.wpz = D.wpy + (size_t)R * L->total_atoms;
+  D.lazy_clash = tu.lazy_clash;
   D.trace = O->trace;
   D.trace_w = 6 + (O->trace ? O->trace_kmax : 0);
   const lg::LigDev Lg = lig_dev(L);
@@ -426,42 +469,87 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   fb[2] = (uint32_t)O->trace_kmax;
   for (uint32_t v : fb) key.push_back(v);
 
+  lg::ClusterBounds cb;
+  std::memset(&cb, 0, sizeof cb);
+  cb.na = tu.n_atom_clusters;
+  cb.nr = tu.n_rot_clusters;
+  for (int c = 0; c < cb.na; ++c) cb.atom[c] = tu.atom_bounds[c];
+  for (int c = 0; c < cb.nr; ++c) cb.rot[c] = tu.rot_bounds[c];
+  // every atom cluster must fit its kernel instance: the last one takes the rest
+  cb.atom[cb.na - 1] = LG_MAX_ATOMS;
+
+  auto plan = [&](std::vector<lg_bucket_stat>& launches) -> lg_status {
+    // Eq. 1: resident blocks per CU of each instance give the persistent grid
+    for (int ca = cb.na - 1; ca >= 0; --ca) {
+      const int nslot = (cb.atom[ca] + 63) / 64;
+      const int wpb = tu.waves_per_block[nslot - 1];
+      int bpc = 0;
+      LG_HIP(lg::occupancy_dock_bucket(nslot, spl, wpb, p->grid.tab_len, &bpc));
+      if (bpc < 1) return fail(LG_ERR_DEVICE, "kernel instance (%d slots, %d samples/lane) cannot be resident", nslot, spl);
+      hipFuncAttributes attr;
+      LG_HIP(lg::attributes_dock_bucket(nslot, spl, &attr));
+      for (int cr = cb.nr - 1; cr >= 0; --cr) {
+        lg_bucket_stat b;
+        b.bucket = ca * cb.nr + cr;
+        b.atom_bound = cb.atom[ca];
+        b.rot_bound = cb.rot[cr];
+        b.slots = nslot;
+        b.samples_per_lane = spl;
+        b.waves_per_block = wpb;
+        b.vgprs = attr.numRegs;
+        b.lds_bytes = (int32_t)((size_t)((p->grid.tab_len + 3) & ~3) * 4 + (size_t)wpb * 3 * 64 * nslot * 16);
+        b.blocks_per_cu = bpc;
+        b.blocks = bpc * p->cus * tu.grid_scale;
+        b.ligands = -1;
+        b.ms = -1.f;
+        launches.push_back(b);
+      }
+    }
+    while (p->events.size() < launches.size() + 1) {
+      hipEvent_t ev;
+      LG_HIP(hipEventCreate(&ev));
+      p->events.push_back(ev);
+    }
+    return LG_OK;
+  };
+  // The whole bucketed sequence on stream `cs`; events between bucket launches.
+  auto enqueue = [&](const std::vector<lg_bucket_stat>& launches, hipStream_t cs, bool events) -> hipError_t {
+    hipError_t e = lg::launch_bucketing(L->atom_offset, L->tors_offset, n, cb, cls, counts, start, fill, perm, cursors, cs);
+    if (e == hipSuccess && events) e = hipEventRecord(p->events[0], cs);
+    for (size_t l = 0; l < launches.size() && e == hipSuccess; ++l) {
+      const lg_bucket_stat& b = launches[l];
+      lg::QueueDev Q{perm, start, cursors, b.bucket, tu.restart_chunk};
+      e = lg::launch_dock_bucket(b.slots, spl, b.waves_per_block, b.blocks, p->grid, Lg, D, Q, cs);
+      if (e == hipSuccess && events) e = hipEventRecord(p->events[l + 1], cs);
+    }
+    if (e == hipSuccess) e = lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, cs);
+    return e;
+  };
+
+  if (!tu.use_graph) {
+    std::vector<lg_bucket_stat> launches;
+    s = plan(launches);
+    if (s != LG_OK) return s;
+    hipError_t e = enqueue(launches, st, true);
+    if (e != hipSuccess) return fail(LG_ERR_DEVICE, "bucketed launch failed: %s", hipGetErrorString(e));
+    p->launches = launches;
+    p->counts_dev = counts;
+    p->timed = true;
+    return LG_OK;
+  }
   if (!p->gexec || key != p->gkey) {
     if (p->gexec) {
       (void)hipGraphExecDestroy(p->gexec);
       p->gexec = nullptr;
       p->gkey.clear();
     }
-    lg::ClusterBounds cb;
-    std::memset(&cb, 0, sizeof cb);
-    cb.na = tu.n_atom_clusters;
-    cb.nr = tu.n_rot_clusters;
-    for (int c = 0; c < cb.na; ++c) cb.atom[c] = tu.atom_bounds[c];
-    for (int c = 0; c < cb.nr; ++c) cb.rot[c] = tu.rot_bounds[c];
-    // every atom cluster must fit its kernel instance: the last one takes the rest
-    cb.atom[cb.na - 1] = LG_MAX_ATOMS;
-    // Eq. 1: resident blocks per CU of each instance; the persistent grid
-    struct Launch { int nslot, wpb, blocks, bucket; };
-    std::vector<Launch> launches;
-    for (int ca = cb.na - 1; ca >= 0; --ca) {
-      const int nslot = (cb.atom[ca] + 63) / 64;
-      const int wpb = tu.waves_per_block[nslot - 1];
-      int bpc = 0;
-      LG_HIP(lg::occupancy_dock_bucket(nslot, spl, wpb, &bpc));
-      if (bpc < 1) return fail(LG_ERR_DEVICE, "kernel instance (%d slots, %d samples/lane) cannot be resident", nslot, spl);
-      for (int cr = cb.nr - 1; cr >= 0; --cr)
-        launches.push_back({nslot, wpb, bpc * p->cus * tu.grid_scale, ca * cb.nr + cr});
-    }
+    std::vector<lg_bucket_stat> launches;
+    s = plan(launches);
+    if (s != LG_OK) return s;
     hipGraph_t graph = nullptr;
     hipStream_t cs = p->capture;
     LG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-    hipError_t e = lg::launch_bucketing(L->atom_offset, L->tors_offset, n, cb, cls, counts, start, fill, perm, cursors, cs);
-    for (const Launch& l : launches) {
-      if (e != hipSuccess) break;
-      lg::QueueDev Q{perm, start, cursors, l.bucket, tu.restart_chunk};
-      e = lg::launch_dock_bucket(l.nslot, spl, l.wpb, l.blocks, p->grid, Lg, D, Q, cs);
-    }
-    if (e == hipSuccess) e = lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, cs);
+    hipError_t e = enqueue(launches, cs, false);
     hipError_t e2 = hipStreamEndCapture(cs, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -474,9 +562,34 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
       return fail(LG_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e3));
     }
     p->gkey = key;
+    p->launches = launches;
+    p->counts_dev = counts;
   }
+  p->timed = false;
   LG_HIP(hipGraphLaunch(p->gexec, st));
   return LG_OK;
+}
+
+int32_t lg_bucket_stats(lg_pocket p, lg_bucket_stat* out, int32_t capacity) {
+  if (!p) return fail(LG_ERR_INVALID_ARG, "pocket is NULL");
+  const int nl = (int)p->launches.size();
+  if (!out || capacity <= 0 || nl == 0) return nl;
+  if (hipDeviceSynchronize() != hipSuccess) return fail(LG_ERR_DEVICE, "device synchronise failed");
+  std::vector<int32_t> counts(p->tuning.n_atom_clusters * p->tuning.n_rot_clusters, 0);
+  if (p->counts_dev &&
+      hipMemcpy(counts.data(), p->counts_dev, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(LG_ERR_DEVICE, "reading bucket counts failed");
+  for (int l = 0; l < nl && l < capacity; ++l) {
+    out[l] = p->launches[l];
+    if (p->launches[l].bucket < (int)counts.size()) out[l].ligands = counts[p->launches[l].bucket];
+    float ms = -1.f;
+    if (p->timed && hipEventElapsedTime(&ms, p->events[l], p->events[l + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      ms = -1.f;
+    }
+    out[l].ms = ms;
+  }
+  return nl;
 }
 
 lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, float* score, float* grad, int32_t top_m,

@@ -8,9 +8,9 @@
 namespace lg {
 
 __device__ __forceinline__ float nearest_s(const GridDev& G, float x, float y, float z) {
-  int ix = clamp_node(fmaf(x - G.o[0], G.inv_h, 0.5f), G.fn[0]);
-  int iy = clamp_node(fmaf(y - G.o[1], G.inv_h, 0.5f), G.fn[1]);
-  int iz = clamp_node(fmaf(z - G.o[2], G.inv_h, 0.5f), G.fn[2]);
+  int ix = clamp_node(fmaf(x, G.inv_h, G.c0[0]), G.fn[0]);
+  int iy = clamp_node(fmaf(y, G.inv_h, G.c0[1]), G.fn[1]);
+  int iz = clamp_node(fmaf(z, G.inv_h, G.c0[2]), G.fn[2]);
   return G.g0[ix + iy * G.stride[1] + iz * G.stride[2]];
 }
 
@@ -157,6 +157,27 @@ __global__ void pad_kernel(const float* src, int nx, int ny, int nz, float out, 
     const bool in = ix >= 1 && ix <= nx && iy >= 1 && iy <= ny && iz >= 1 && iz <= nz;
     dst[idx] = in ? src[((iz - 1) * ny + (iy - 1)) * nx + (ix - 1)] : out;
   }
+}
+
+// Copy of the padded grid in 4x4x2 bricks (see GridDev); nodes past the padded
+// extent (brick round-up) hold out_value and are never addressed.
+__global__ void brick_kernel(const float* padded, int px, int py, int pz, int nbx, int nby, int nbz, float out,
+                             float* brick) {
+  const long long total = (long long)nbx * nby * nbz * 32;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long b = e >> 5;
+    const int w = (int)(e & 31);
+    const int bx = (int)(b % nbx), by = (int)((b / nbx) % nby), bz = (int)(b / ((long long)nbx * nby));
+    const int X = 4 * bx + (w & 3), Y = 4 * by + ((w >> 2) & 3), Z = 2 * bz + (w >> 4);
+    brick[e] = (X < px && Y < py && Z < pz) ? padded[((long long)Z * py + Y) * px + X] : out;
+  }
+}
+
+hipError_t launch_brick(const float* padded, int px, int py, int pz, int nbx, int nby, int nbz, float out,
+                        float* brick, hipStream_t st) {
+  hipLaunchKernelGGL(brick_kernel, dim3(1024), dim3(256), 0, st, padded, px, py, pz, nbx, nby, nbz, out, brick);
+  return hipGetLastError();
 }
 
 hipError_t launch_pad(const float* src, int nx, int ny, int nz, float out, float* dst, hipStream_t st) {

@@ -34,11 +34,18 @@ struct SampleReg {
   uint32_t valid_a, valid_t;   // bit q: sample lane + 64 q exists
 };
 
+__device__ __forceinline__ int node_off(const GridDev& G, float x, float y, float z) {
+  int ix = clamp_node(fmaf(x, G.inv_h, G.c0[0]), G.fn[0]);
+  int iy = clamp_node(fmaf(y, G.inv_h, G.c0[1]), G.fn[1]);
+  int iz = clamp_node(fmaf(z, G.inv_h, G.c0[2]), G.fn[2]);
+  return mad24(ix, G.bs[0], mad24(iy, G.bs[1], mad24(iz, G.bs[2], G.b0)));
+}
+
+// Brick byte offset of node index i in [-1, n] from an axis table (t = tab + base + 1).
+__device__ __forceinline__ int boff(const int* t, int i) { return t[i]; }
+
 __device__ __forceinline__ float nearest(const GridDev& G, float x, float y, float z) {
-  int ix = clamp_node(fmaf(x - G.o[0], G.inv_h, 0.5f), G.fn[0]);
-  int iy = clamp_node(fmaf(y - G.o[1], G.inv_h, 0.5f), G.fn[1]);
-  int iz = clamp_node(fmaf(z - G.o[2], G.inv_h, 0.5f), G.fn[2]);
-  return G.g0[ix + iy * G.stride[1] + iz * G.stride[2]];
+  return grid_at(G.gb, node_off(G, x, y, z));
 }
 
 // Trilinear value (and gradient if g != nullptr); same op order as the oracle.
@@ -118,10 +125,39 @@ __device__ __forceinline__ void mat_apply(const float m[9], float vx, float vy, 
   y2 = fmaf(m[8], vz, fmaf(m[7], vy, m[6] * vx));
 }
 
+// acc[q] += gather(t)[q] over t < n, with the gathers of atom t+1 issued before
+// the values of atom t are added (two register buffers, no copies).
+template <int Q, int NA, class F>
+__device__ __forceinline__ void pipelined_sum(int n, F gather, float (&acc)[NA], int qoff = 0) {
+  float v0[Q], v1[Q];
+  gather(0, v0);
+  int t = 1;
+  for (; t + 1 < n; t += 2) {
+    gather(t, v1);
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads of atom t ahead of the sums of atom t-1
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q + qoff] += v0[q];
+    gather(t + 1, v0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q + qoff] += v1[q];
+  }
+  if (t < n) {
+    gather(t, v1);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q + qoff] += v0[q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q + qoff] += v1[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q + qoff] += v0[q];
+  }
+}
+
 // ---- rigid rotation scan about lab axis E through the pivot ------------------
 template <int NSLOT, int SPL, int E>
 __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr,
-                        const SampleReg<SPL>& sm) {
+                        const SampleReg<SPL>& sm, const int* tab) {
   constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
   const int lane = lane_id();
   float s0 = 0.f;
@@ -130,8 +166,8 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
     const int a = s * 64 + lane;
     if (a < N) {
       float vp = p.x[P][s] - p.piv[P], vq = p.x[Q][s] - p.piv[Q];
-      int ie = clamp_node(fmaf(p.x[E][s] - G.o[E], G.inv_h, 0.5f), G.fn[E]);
-      scr[a] = make_float4(vp, vq, __int_as_float(ie * G.stride[E]), 0.f);
+      int ie = clamp_node(fmaf(p.x[E][s], G.inv_h, G.c0[E]), G.fn[E]);
+      scr[a] = make_float4(vp, vq, __int_as_float(boff(tab + G.tab_base[E] + 1, ie)), 0.f);
       s0 += nearest(G, p.x[0][s], p.x[1][s], p.x[2][s]);
     }
   }
@@ -141,10 +177,12 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
 #pragma unroll
   for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
   const float pP = p.piv[P], pQ = p.piv[Q];
-  const float oP = G.o[P], oQ = G.o[Q], ih = G.inv_h, fnP = G.fn[P], fnQ = G.fn[Q];
-  const int sP = G.stride[P], sQ = G.stride[Q];
-  const float* g0 = G.g0;
-  for (int t = 0; t < N; ++t) {
+  const float cP = G.c0[P], cQ = G.c0[Q], ih = G.inv_h, fnP = G.fn[P], fnQ = G.fn[Q];
+  const int* tP = tab + G.tab_base[P] + 1;
+  const int* tQ = tab + G.tab_base[Q] + 1;
+  const char* gk = G.gk;
+  // gathers of atom t+1 are issued before the values of atom t are summed
+  auto gather = [&](int t, float (&out)[SPL]) {
     const float4 d = scr[t];
     const int part = __float_as_int(d.z);
 #pragma unroll
@@ -152,11 +190,12 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
       float np = fmaf(sm.c[q], d.x, -(sm.s[q] * d.y));
       float nq = fmaf(sm.s[q], d.x, sm.c[q] * d.y);
       float xp = pP + np, xq = pQ + nq;
-      int ip = clamp_node(fmaf(xp - oP, ih, 0.5f), fnP);
-      int iq = clamp_node(fmaf(xq - oQ, ih, 0.5f), fnQ);
-      acc[q] += g0[part + ip * sP + iq * sQ];
+      int ip = clamp_node(fmaf(xp, ih, cP), fnP);
+      int iq = clamp_node(fmaf(xq, ih, cQ), fnQ);
+      out[q] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
     }
-  }
+  };
+  pipelined_sum<SPL>(N, gather, acc);
   if (lane == 0) acc[0] = s0;   // sample 0 is the current pose
   const int j = wave_argmax(acc, sm.valid_a);
   if (j != 0) {
@@ -177,35 +216,37 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
 // ---- rigid translation scan along lab axis E ---------------------------------
 template <int NSLOT, int SPL, int E>
 __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr,
-                          const SampleReg<SPL>& sm) {
+                          const SampleReg<SPL>& sm, const int* tab) {
   constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
   const int lane = lane_id();
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const int a = s * 64 + lane;
     if (a < N) {
-      int ip = clamp_node(fmaf(p.x[P][s] - G.o[P], G.inv_h, 0.5f), G.fn[P]);
-      int iq = clamp_node(fmaf(p.x[Q][s] - G.o[Q], G.inv_h, 0.5f), G.fn[Q]);
-      scr[a] = make_float4(p.x[E][s], __int_as_float(ip * G.stride[P] + iq * G.stride[Q]), 0.f, 0.f);
+      int ip = clamp_node(fmaf(p.x[P][s], G.inv_h, G.c0[P]), G.fn[P]);
+      int iq = clamp_node(fmaf(p.x[Q][s], G.inv_h, G.c0[Q]), G.fn[Q]);
+      const int part = boff(tab + G.tab_base[P] + 1, ip) + boff(tab + G.tab_base[Q] + 1, iq);
+      scr[a] = make_float4(p.x[E][s], __int_as_float(part), 0.f, 0.f);
     }
   }
   wave_sync();
   float acc[SPL];
 #pragma unroll
   for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
-  const float oE = G.o[E], ih = G.inv_h, fnE = G.fn[E];
-  const int sE = G.stride[E];
-  const float* g0 = G.g0;
-  for (int t = 0; t < N; ++t) {
+  const float cE = G.c0[E], ih = G.inv_h, fnE = G.fn[E];
+  const int* tE = tab + G.tab_base[E] + 1;
+  const char* gk = G.gk;
+  auto gather = [&](int t, float (&out)[SPL]) {
     const float4 d = scr[t];
     const int part = __float_as_int(d.y);
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
       float xe = d.x + sm.d[q];
-      int ie = clamp_node(fmaf(xe - oE, ih, 0.5f), fnE);
-      acc[q] += g0[part + ie * sE];
+      int ie = clamp_node(fmaf(xe, ih, cE), fnE);
+      out[q] = grid_at(gk, part + boff(tE, ie));
     }
-  }
+  };
+  pipelined_sum<SPL>(N, gather, acc);
   const int j = wave_argmax(acc, sm.valid_t);
   if (j != 0) {
     const int m = j < D.T / 2 ? j : j - D.T;
@@ -219,10 +260,19 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
 }
 
 // ---- greedy torsion scan of bond k with the clash check ----------------------
+// Admissibility of every sample is decided in the scoring pass.  A moving atom
+// sweeps a circle about the bond axis; a (moving, static) pair whose circle never
+// comes within clash distance + margin of the static atom cannot clash at any
+// angle (the margin is far above the FP32 deviation of the computed rotation from
+// the exact circle), so only the remaining "risky" pairs are tested, with the
+// oracle's d^2 formula.  The pairs are listed in LDS grouped by moving atom; if
+// a scan has more risky pairs than the list holds, the winner is instead tested
+// against every pair and dropped while it clashes (same result, slower).
 template <int NSLOT, int SPL>
 __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, PoseReg<NSLOT>& p, int N,
-                         int toff, int k, const uint32_t (&mk)[NSLOT], float4* scr, float4* cand,
-                         const SampleReg<SPL>& sm) {
+                         int toff, int k, const uint32_t (&mk)[NSLOT], float4* scr, float4* pairs,
+                         const SampleReg<SPL>& sm, const int* tab) {
+  constexpr int PAIR_CAP = 128 * NSLOT;
   const int lane = lane_id();
   const int a = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k)]);
   const int b = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k) + 1]);
@@ -231,8 +281,10 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
   const float xb = atom_value(p.x[0], b), yb = atom_value(p.x[1], b), zb = atom_value(p.x[2], b);
   const float ux = (xb - xa) * il, uy = (yb - ya) * il, uz = (zb - za) * il;
 
-  // moving atoms of F_k other than b, compacted into scr; their current score
+  // moving atoms of F_k other than b, compacted into scr; their current score;
+  // axial position h and radius r of every static atom about the bond axis
   bool mv[NSLOT], st[NSLOT];
+  float hs[NSLOT], rs[NSLOT];
   int m = 0;
   float s0 = 0.f;
 #pragma unroll
@@ -242,10 +294,13 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
     const bool inf = in && ((mk[s] >> k) & 1u);
     mv[s] = inf && at != b;
     st[s] = in && !inf && at != a;
+    const float vx = p.x[0][s] - xa, vy = p.x[1][s] - ya, vz = p.x[2][s] - za;
+    hs[s] = vx * ux + vy * uy + vz * uz;
+    rs[s] = sqrtf(fmaxf(vx * vx + vy * vy + vz * vz - hs[s] * hs[s], 0.f));
     const uint64_t bal = __ballot(mv[s]);
     const int pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
     if (mv[s]) {
-      scr[m + pre] = make_float4(p.x[0][s] - xa, p.x[1][s] - ya, p.x[2][s] - za, 0.f);
+      scr[m + pre] = make_float4(vx, vy, vz, 0.f);
       s0 += nearest(G, p.x[0][s], p.x[1][s], p.x[2][s]);
     }
     m += __popcll(bal);
@@ -253,62 +308,114 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
   s0 = wave_sum(s0);
   wave_sync();
 
+  // risky pairs, grouped by moving atom t; scr[t].w = first pair | count << 16
+  int npairs = 0;
+  for (int t = 0; t < m; ++t) {
+    const float4 v = scr[t];
+    const float ht = v.x * ux + v.y * uy + v.z * uz;
+    const float rt = sqrtf(fmaxf(v.x * v.x + v.y * v.y + v.z * v.z - ht * ht, 0.f));
+    const int first = npairs;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const float dh = ht - hs[s], dr = rt - rs[s];
+      const bool risky = st[s] && fmaf(dr, dr, dh * dh) < D.clash_r2;
+      const uint64_t bal = __ballot(risky);
+      const int pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (risky && npairs + pre < PAIR_CAP) pairs[npairs + pre] = make_float4(p.x[0][s], p.x[1][s], p.x[2][s], 0.f);
+      npairs += __popcll(bal);
+    }
+    if (lane == 0) reinterpret_cast<int*>(scr + t)[3] = min(first, PAIR_CAP) | ((npairs - first) << 16);
+  }
+  const bool overflow = npairs > PAIR_CAP || D.lazy_clash;
+  wave_sync();
+
   float acc[SPL];
 #pragma unroll
   for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
-  constexpr int QG = SPL < 4 ? SPL : 4;
-  const float ih = G.inv_h;
-  const float* g0 = G.g0;
-  const int s1 = G.stride[1], s2 = G.stride[2];
+  uint32_t clash = 0u;   // bit q: sample lane + 64 q clashes
+  constexpr int QG = SPL < 2 ? SPL : 2;   // samples whose matrices are held at once
+  const float ih = G.inv_h, clash2 = D.clash2;
+  const char* gk = G.gk;
+  const int* tX = tab + G.tab_base[0] + 1;
+  const int* tY = tab + G.tab_base[1] + 1;
+  const int* tZ = tab + G.tab_base[2] + 1;
+  if (m > 0) {
 #pragma unroll
-  for (int g = 0; g < SPL; g += QG) {
-    float M[QG][9];
+    for (int g = 0; g < SPL; g += QG) {
+      float M[QG][9];
 #pragma unroll
-    for (int q = 0; q < QG; ++q) torsion_matrix(ux, uy, uz, sm.c[g + q], sm.s[g + q], M[q]);
-    for (int t = 0; t < m; ++t) {
-      const float4 v = scr[t];
+      for (int q = 0; q < QG; ++q) torsion_matrix(ux, uy, uz, sm.c[g + q], sm.s[g + q], M[q]);
+      auto gather = [&](int t, float (&out)[QG]) {
+        const float4 v = scr[t];
+        float X[QG], Y[QG], Z[QG];
 #pragma unroll
-      for (int q = 0; q < QG; ++q) {
-        float y0, y1, y2;
-        mat_apply(M[q], v.x, v.y, v.z, y0, y1, y2);
-        float x = xa + y0, y = ya + y1, z = za + y2;
-        int ix = clamp_node(fmaf(x - G.o[0], ih, 0.5f), G.fn[0]);
-        int iy = clamp_node(fmaf(y - G.o[1], ih, 0.5f), G.fn[1]);
-        int iz = clamp_node(fmaf(z - G.o[2], ih, 0.5f), G.fn[2]);
-        acc[g + q] += g0[ix + iy * s1 + iz * s2];
-      }
+        for (int q = 0; q < QG; ++q) {
+          float y0, y1, y2;
+          mat_apply(M[q], v.x, v.y, v.z, y0, y1, y2);
+          X[q] = xa + y0;
+          Y[q] = ya + y1;
+          Z[q] = za + y2;
+          int ix = clamp_node(fmaf(X[q], ih, G.c0[0]), G.fn[0]);
+          int iy = clamp_node(fmaf(Y[q], ih, G.c0[1]), G.fn[1]);
+          int iz = clamp_node(fmaf(Z[q], ih, G.c0[2]), G.fn[2]);
+          out[q] = grid_at(gk, boff(tX, ix) + boff(tY, iy) + boff(tZ, iz));
+        }
+        if (!overflow) {
+          const int seg = __float_as_int(v.w);
+          const int p0 = seg & 0xFFFF, p1 = p0 + (seg >> 16);
+          for (int pi = p0; pi < p1; ++pi) {
+            const float4 c = pairs[pi];
+#pragma unroll
+            for (int q = 0; q < QG; ++q) {
+              float dx = X[q] - c.x, dy = Y[q] - c.y, dz = Z[q] - c.z;
+              float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              if (d2 < clash2) clash |= 1u << (g + q);
+            }
+          }
+        }
+      };
+      pipelined_sum<QG>(m, gather, acc, g);
     }
   }
-  if (lane == 0) acc[0] = s0;
+  if (lane == 0) {
+    acc[0] = s0;        // sample 0 is the current pose,
+    clash &= ~1u;       // always admissible
+  }
 
-  // best sample; a winner that clashes is dropped and the next best taken
-  uint32_t alive = sm.valid_a;
   int j;
   float Mj[9];
-  for (;;) {
-    j = wave_argmax(acc, alive);
-    if (j == 0) break;
-    torsion_matrix(ux, uy, uz, D.angles[2 * j], D.angles[2 * j + 1], Mj);
-    for (int t = lane; t < m; t += 64) {
-      const float4 v = scr[t];
-      float y0, y1, y2;
-      mat_apply(Mj, v.x, v.y, v.z, y0, y1, y2);
-      cand[t] = make_float4(xa + y0, ya + y1, za + y2, 0.f);
-    }
-    wave_sync();
-    bool clash = false;
-    for (int t = 0; t < m; ++t) {
-      const float4 c = cand[t];
-#pragma unroll
-      for (int s = 0; s < NSLOT; ++s) {
-        float dx = c.x - p.x[0][s], dy = c.y - p.x[1][s], dz = c.z - p.x[2][s];
-        float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        clash |= st[s] && d2 < D.clash2;
+  if (!overflow) {
+    j = wave_argmax(acc, sm.valid_a & ~clash);
+    if (j != 0) torsion_matrix(ux, uy, uz, D.angles[2 * j], D.angles[2 * j + 1], Mj);
+  } else {
+    // best sample; a winner that clashes is dropped and the next best taken
+    float4* cand = pairs;
+    uint32_t alive = sm.valid_a;
+    for (;;) {
+      j = wave_argmax(acc, alive);
+      if (j == 0) break;
+      torsion_matrix(ux, uy, uz, D.angles[2 * j], D.angles[2 * j + 1], Mj);
+      for (int t = lane; t < m; t += 64) {
+        const float4 v = scr[t];
+        float y0, y1, y2;
+        mat_apply(Mj, v.x, v.y, v.z, y0, y1, y2);
+        cand[t] = make_float4(xa + y0, ya + y1, za + y2, 0.f);
       }
+      wave_sync();
+      bool hit = false;
+      for (int t = 0; t < m; ++t) {
+        const float4 c = cand[t];
+#pragma unroll
+        for (int s = 0; s < NSLOT; ++s) {
+          float dx = c.x - p.x[0][s], dy = c.y - p.x[1][s], dz = c.z - p.x[2][s];
+          float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          hit |= st[s] && d2 < clash2;
+        }
+      }
+      if (!wave_any(hit)) break;
+      if (lane == (j & 63)) alive &= ~(1u << (j >> 6));
+      wave_sync();
     }
-    if (!wave_any(clash)) break;
-    if (lane == (j & 63)) alive &= ~(1u << (j >> 6));
-    wave_sync();
   }
   if (j != 0) {
 #pragma unroll
@@ -383,7 +490,7 @@ __device__ void load_ligand(const LigDev& Lg, int lig, LigReg<NSLOT>& L) {
 // One restart: placement, S sweeps, final trilinear score, outputs.
 template <int NSLOT, int SPL>
 __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& D, const SampleReg<SPL>& sm,
-                             const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand) {
+                             const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand, const int* tab) {
   const int lane = lane_id();
   const int N = L.N;
   PoseReg<NSLOT> p;
@@ -405,19 +512,19 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
 
   int16_t* tr = D.trace ? D.trace + ((size_t)lig * D.R + r) * (size_t)D.S * D.trace_w : nullptr;
   for (int sw = 0; sw < D.S; ++sw) {
-    int jr0 = rot_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm);
-    int jr1 = rot_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm);
-    int jr2 = rot_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm);
-    int jt0 = trans_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm);
-    int jt1 = trans_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm);
-    int jt2 = trans_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm);
+    int jr0 = rot_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm, tab);
+    int jr1 = rot_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm, tab);
+    int jr2 = rot_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm, tab);
+    int jt0 = trans_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm, tab);
+    int jt1 = trans_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm, tab);
+    int jt2 = trans_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm, tab);
     int16_t* trow = tr ? tr + (size_t)sw * D.trace_w : nullptr;
     if (trow && lane == 0) {
       trow[0] = (int16_t)jr0; trow[1] = (int16_t)jr1; trow[2] = (int16_t)jr2;
       trow[3] = (int16_t)jt0; trow[4] = (int16_t)jt1; trow[5] = (int16_t)jt2;
     }
     for (int k = 0; k < L.K; ++k) {
-      int jk = tors_scan<NSLOT, SPL>(G, Lg, D, p, N, L.toff, k, L.mk, scr, cand, sm);
+      int jk = tors_scan<NSLOT, SPL>(G, Lg, D, p, N, L.toff, k, L.mk, scr, cand, sm, tab);
       if (trow && lane == 0) trow[6 + k] = (int16_t)jk;
     }
   }
@@ -447,11 +554,18 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
 }
 
 // Plain method: one launch per ligand; wavefront w of the grid docks restart w.
+// LDS of a block: the brick offset tables, then per wavefront the scan data of
+// 64*NSLOT atoms and a list of 128*NSLOT risky torsion pairs.
+__device__ __forceinline__ int tab_words(const GridDev& G) { return (G.tab_len + 3) & ~3; }
+
 template <int NSLOT, int SPL>
 __global__ __launch_bounds__(256) void dock_plain_kernel(GridDev G, LigDev Lg, DockDev D, int lig) {
   extern __shared__ float4 lds[];
+  int* tab = reinterpret_cast<int*>(lds);
+  fill_brick_tables(G, tab);
+  __syncthreads();
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  float4* scr = lds + (size_t)wave * (2 * 64 * NSLOT);
+  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * (3 * 64 * NSLOT);
   float4* cand = scr + 64 * NSLOT;
   const int r = blockIdx.x * nwaves + wave;
   if (r >= D.R) return;
@@ -459,7 +573,7 @@ __global__ __launch_bounds__(256) void dock_plain_kernel(GridDev G, LigDev Lg, D
   load_samples(D, sm);
   LigReg<NSLOT> L;
   load_ligand(Lg, lig, L);
-  dock_restart(G, Lg, D, sm, L, lig, r, scr, cand);
+  dock_restart(G, Lg, D, sm, L, lig, r, scr, cand, tab);
 }
 
 // Bucketed method: persistent; wavefronts pull (ligand, restart chunk) items of
@@ -467,8 +581,11 @@ __global__ __launch_bounds__(256) void dock_plain_kernel(GridDev G, LigDev Lg, D
 template <int NSLOT, int SPL>
 __global__ __launch_bounds__(256) void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
   extern __shared__ float4 lds[];
+  int* tab = reinterpret_cast<int*>(lds);
+  fill_brick_tables(G, tab);
+  __syncthreads();
   const int wave = threadIdx.x >> 6;
-  float4* scr = lds + (size_t)wave * (2 * 64 * NSLOT);
+  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * (3 * 64 * NSLOT);
   float4* cand = scr + 64 * NSLOT;
   const int lane = lane_id();
   const int b0 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket]);
@@ -492,7 +609,7 @@ __global__ __launch_bounds__(256) void dock_bucket_kernel(GridDev G, LigDev Lg, 
       cur_lig = lig;
     }
     const int r0 = ch * Q.chunk, r1 = min(D.R, r0 + Q.chunk);
-    for (int r = r0; r < r1; ++r) dock_restart(G, Lg, D, sm, L, lig, r, scr, cand);
+    for (int r = r0; r < r1; ++r) dock_restart(G, Lg, D, sm, L, lig, r, scr, cand, tab);
   }
 }
 
@@ -537,7 +654,9 @@ __global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, 
 
 // ---------------------------------------------------------------- dispatch
 // LDS per block: per wavefront, scan data and torsion candidates of 64*NSLOT atoms.
-static size_t lds_bytes(int nslot, int wpb) { return (size_t)wpb * 2 * 64 * nslot * sizeof(float4); }
+static size_t lds_bytes(int nslot, int wpb, int tab_len) {
+  return (size_t)((tab_len + 3) & ~3) * sizeof(int) + (size_t)wpb * 3 * 64 * nslot * sizeof(float4);
+}
 
 #define LG_DISPATCH(nslot, spl, CALL)                                          \
   switch (nslot * 100 + spl) {                                                 \
@@ -558,7 +677,7 @@ hipError_t launch_dock_plain(int nslot, int spl, int wpb, const GridDev& G, cons
 #define CALL(NS, SP)                                                                            \
   {                                                                                             \
     hipLaunchKernelGGL((dock_plain_kernel<NS, SP>), dim3(blocks), dim3(64 * wpb),               \
-                       lds_bytes(NS, wpb), st, G, Lg, D, lig);                              \
+                       lds_bytes(NS, wpb, G.tab_len), st, G, Lg, D, lig);                              \
     return hipGetLastError();                                                                   \
   }
   LG_DISPATCH(nslot, spl, CALL)
@@ -570,7 +689,7 @@ hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const Gri
 #define CALL(NS, SP)                                                                            \
   {                                                                                             \
     hipLaunchKernelGGL((dock_bucket_kernel<NS, SP>), dim3(blocks), dim3(64 * wpb),              \
-                       lds_bytes(NS, wpb), st, G, Lg, D, Q);                                \
+                       lds_bytes(NS, wpb, G.tab_len), st, G, Lg, D, Q);                                \
     return hipGetLastError();                                                                   \
   }
   LG_DISPATCH(nslot, spl, CALL)
@@ -578,12 +697,19 @@ hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const Gri
 }
 
 // Resident blocks per compute unit of a bucket kernel instance (the b of Eq. 1).
-hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int* blocks_per_cu) {
+hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int tab_len, int* blocks_per_cu) {
 #define CALL(NS, SP)                                                                                  \
   {                                                                                                   \
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, dock_bucket_kernel<NS, SP>,    \
-                                                        64 * wpb, lds_bytes(NS, wpb));            \
+                                                        64 * wpb, lds_bytes(NS, wpb, tab_len));            \
   }
+  LG_DISPATCH(nslot, spl, CALL)
+#undef CALL
+}
+
+hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr) {
+#define CALL(NS, SP) \
+  { return hipFuncGetAttributes(attr, reinterpret_cast<const void*>(dock_bucket_kernel<NS, SP>)); }
   LG_DISPATCH(nslot, spl, CALL)
 #undef CALL
 }

@@ -14,6 +14,18 @@ namespace lg {
 // padded node (1,1,1) = logical node (0,0,0); strides are the padded ones.
 struct GridDev {
   const float* g0;
+  const char* gb;   // padded grid, byte addressed: node (ix,iy,iz) in [-1,n]^3 sits at
+  int bs[3];        //   gb + b0 + ix*bs[0] + iy*bs[1] + iz*bs[2] (bs = byte strides 4, 4(nx+2), ...)
+  int b0;           //   b0 = byte offset of logical node (0,0,0); every offset is >= 0 and < 2^31
+  // The scans read a second copy in 4x4x2-node bricks, one 128-byte cache line
+  // each, so the samples of one lookup instruction (an arc or a short segment)
+  // touch few lines.  Byte offset of padded node (px,py,pz) = Tx[px]+Ty[py]+Tz[pz]
+  // with per-axis tables built in LDS by every block (brick_tables).
+  const char* gk;
+  int nb[3];        // bricks per axis
+  int tab_base[3];  // first entry of each axis table in the LDS table array
+  int tab_len;      // (nx+2)+(ny+2)+(nz+2) entries
+  float c0[3];      // nearest-node map: f = fma(x, inv_h, c0), c0 = fma(-o, inv_h, 0.5)
   int n[3];
   int stride[3];    // 1, nx+2, (nx+2)(ny+2)
   float o[3];
@@ -38,6 +50,8 @@ struct LigDev {
 struct DockDev {
   int R, A, T, S;
   float delta, clash2;
+  float clash_r2;          // (sqrt(clash2) + margin)^2: pairs farther apart on their circles never clash
+  int lazy_clash;          // 1: no pair list, test only the winner of each torsion scan
   float c[3];
   const float* restarts;   // [R][12]
   const float* angles;     // [A][2]
@@ -98,6 +112,30 @@ struct OpAddF {
 };
 
 __device__ __forceinline__ float wave_sum(float v) { return __int_as_float(wave_reduce_i32(__float_as_int(v), OpAddF())); }
+
+// Per-axis byte-offset tables of the brick layout, indexed by padded node
+// coordinate p in [0, n+1]: x (p>>2)*128 + (p&3)*4, y (p>>2)*128*nbx + (p&3)*16,
+// z (p>>1)*128*nbx*nby + (p&1)*64.  Filled by all threads of a block.
+__device__ __forceinline__ void fill_brick_tables(const GridDev& G, int* tab) {
+  for (int k = threadIdx.x; k < G.tab_len; k += blockDim.x) {
+    int a = k < G.tab_base[1] ? 0 : (k < G.tab_base[2] ? 1 : 2);
+    int p = k - G.tab_base[a];
+    int v;
+    if (a == 0) v = (p >> 2) * 128 + (p & 3) * 4;
+    else if (a == 1) v = (p >> 2) * 128 * G.nb[0] + (p & 3) * 16;
+    else v = (p >> 1) * 128 * G.nb[0] * G.nb[1] + (p & 1) * 64;
+    tab[k] = v;
+  }
+}
+
+// 24-bit signed multiply-add (full-rate v_mad_i32_i24); |a| <= 1025, |b| < 2^23.
+__device__ __forceinline__ int mad24(int a, int b, int c) { return __mul24(a, b) + c; }
+
+// Grid value at a non-negative byte offset from the padded base (32-bit offset,
+// scalar base address).
+__device__ __forceinline__ float grid_at(const char* gb, int off) {
+  return *reinterpret_cast<const float*>(gb + (uint32_t)off);
+}
 
 // Order-preserving map of a float to a signed int (total order on non-NaN).
 __device__ __forceinline__ int orderable(float f) {

@@ -26,8 +26,8 @@ LG_PLAIN, LG_BUCKETED = 0, 1
 LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
 
 EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_set_tuning",
-           "lg_get_tuning", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters", "lg_last_error",
-           "lg_version")
+           "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
+           "lg_last_error", "lg_version")
 
 
 class LgError(RuntimeError):
@@ -72,7 +72,15 @@ class lg_refine_params(ctypes.Structure):
 class lg_tuning(ctypes.Structure):
     _fields_ = [("n_atom_clusters", c_int32), ("atom_bounds", c_int32 * 16), ("n_rot_clusters", c_int32),
                 ("rot_bounds", c_int32 * 32), ("waves_per_block", c_int32 * 4), ("restart_chunk", c_int32),
-                ("grid_scale", c_int32), ("plain_waves_per_block", c_int32)]
+                ("grid_scale", c_int32), ("plain_waves_per_block", c_int32), ("use_graph", c_int32),
+                ("lazy_clash", c_int32)]
+
+
+class lg_bucket_stat(ctypes.Structure):
+    _fields_ = [("bucket", c_int32), ("atom_bound", c_int32), ("rot_bound", c_int32), ("slots", c_int32),
+                ("samples_per_lane", c_int32), ("waves_per_block", c_int32), ("vgprs", c_int32),
+                ("lds_bytes", c_int32), ("blocks_per_cu", c_int32), ("blocks", c_int32), ("ligands", c_int32),
+                ("ms", c_float)]
 
 
 _lib = None
@@ -97,6 +105,8 @@ def load_library(path: str = LIB_PATH):
                               c_void_p, c_void_p]
     lib.lg_set_tuning.argtypes = [c_void_p, P(lg_tuning)]
     lib.lg_get_tuning.argtypes = [c_void_p, P(lg_tuning)]
+    lib.lg_bucket_stats.argtypes = [c_void_p, P(lg_bucket_stat), c_int32]
+    lib.lg_bucket_stats.restype = c_int32
     lib.lg_bucket_size.argtypes = [ctypes.c_int64] * 4
     lib.lg_bucket_size.restype = ctypes.c_int64
     lib.lg_atom_clusters.argtypes = [c_int32, c_int32, c_int32, P(c_int32)]
@@ -238,6 +248,15 @@ class Pocket:
 
     def set_tuning(self, tuning: lg_tuning):
         _check(_lib.lg_set_tuning(self.handle, ctypes.byref(tuning)))
+
+    def bucket_stats(self) -> list:
+        """lg_bucket_stats of the last bucketed call, as dicts."""
+        cap = 64
+        buf = (lg_bucket_stat * cap)()
+        n = _lib.lg_bucket_stats(self.handle, buf, cap)
+        if n < 0:
+            _check(n)
+        return [{f: getattr(buf[i], f) for f, _ in lg_bucket_stat._fields_} for i in range(min(n, cap))]
 
     def get_tuning(self) -> lg_tuning:
         t = lg_tuning()

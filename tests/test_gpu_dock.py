@@ -62,6 +62,14 @@ def test_ragged_sizes_and_sample_counts(lgmod, tiny, A, T):
     plain = dock_gpu(pocket, L, r32, a32, mode=lg.LG_PLAIN, **kw)
     for key in plain:
         np.testing.assert_array_equal(plain[key], buck[key], err_msg=f"plain vs bucketed: {key}")
+    t = pocket.get_tuning()
+    z = lg.lg_tuning.from_buffer_copy(t)
+    z.lazy_clash = 1
+    pocket.set_tuning(z)
+    lazy = dock_gpu(pocket, L, r32, a32, mode=lg.LG_BUCKETED, **kw)
+    pocket.set_tuning(t)
+    for key in plain:
+        np.testing.assert_array_equal(lazy[key], buck[key], err_msg=f"winner-only clash test: {key}")
     for i in range(L.n):
         ref = dock_oracle(pk, L, i, r32, a32, T=T, S=1)
         compare_ligand(buck, L, i, ref, np.arange(5), 3, 5, f"ragged A={A}")
@@ -104,6 +112,37 @@ def test_determinism_and_batch_order(lgmod, tiny):
     b = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], **kw)
     for key in a:
         np.testing.assert_array_equal(a[key], b[key])
+    # launched directly (no graph, events between the bucket launches): same bits
+    t = pocket.get_tuning()
+    e = lg.lg_tuning.from_buffer_copy(t)
+    e.use_graph = 0
+    pocket.set_tuning(e)
+    d = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], **kw)
+    stats = pocket.bucket_stats()
+    pocket.set_tuning(t)
+    for key in a:
+        np.testing.assert_array_equal(a[key], d[key])
+    assert sum(b["ligands"] for b in stats) == L.n
+    assert all(b["ms"] >= 0 for b in stats)
+    # other tunings (one bucket, rotamer clusters, chunking): same bits
+    o = lg.lg_tuning.from_buffer_copy(t)
+    o.n_atom_clusters, o.n_rot_clusters, o.restart_chunk = 2, 3, 3
+    o.atom_bounds[0], o.atom_bounds[1] = 30, 256
+    o.rot_bounds[0], o.rot_bounds[1], o.rot_bounds[2] = 2, 4, 32
+    o.waves_per_block[0], o.grid_scale = 1, 2
+    pocket.set_tuning(o)
+    f = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], **kw)
+    pocket.set_tuning(t)
+    for key in a:
+        np.testing.assert_array_equal(a[key], f[key])
+    # clash test of the winner only (no pruned pair list): same bits
+    z = lg.lg_tuning.from_buffer_copy(t)
+    z.lazy_clash = 1
+    pocket.set_tuning(z)
+    g = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], **kw)
+    pocket.set_tuning(t)
+    for key in a:
+        np.testing.assert_array_equal(a[key], g[key])
     perm = np.random.default_rng(1).permutation(L.n)
     Lp = L.subset(perm)
     c = dock_gpu(pocket, Lp, tiny["r32"], tiny["a32"], **kw)
