@@ -71,6 +71,8 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.oracle_score.restype = ctypes.c_double
         lib.oracle_pose_grad.restype = ctypes.c_double
+        lib.oracle_refine.restype = ctypes.c_double
+        lib.oracle_move_grad.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -215,6 +217,63 @@ def pose_map(lig, xyz, P, q):
     out = np.zeros_like(x)
     lib.oracle_pose_map(ctypes.byref(L), _p(x), _p(Pp), _p(qq), _p(out))
     return out
+
+
+REFINE_DEFAULTS = dict(steps=50, eta_t=1e-2, eta_w=1e-3, eta_th=1e-3, clip_t=0.1, clip_w=0.05, clip_th=0.1)
+
+
+def refine(lig, pocket, xyz, P, bits=32, fp64_input=False, clash2=None, **kw):
+    """Refine one pose; returns (best_score, best_xyz [N,3], accepted_steps)."""
+    lib = _load()
+    keep = _Keep()
+    g = _grid(pocket, keep)
+    L = _lig(lig, keep, fp64_input)
+    x = keep(np.asarray(xyz).reshape(-1, 3), np.float64)
+    L.xyz = _p(x)
+    Pp = keep(P, np.float64)
+    prm = dict(REFINE_DEFAULTS, **kw)
+    arr = keep(np.array([prm["steps"], prm["eta_t"], prm["eta_w"], prm["eta_th"], prm["clip_t"], prm["clip_w"],
+                         prm["clip_th"], CLASH2 if clash2 is None else clash2], np.float64), np.float64)
+    out = np.zeros_like(x)
+    acc = ctypes.c_int(0)
+    s = lib.oracle_refine(ctypes.c_int(bits), ctypes.byref(g), ctypes.byref(L), _p(Pp), _p(arr), _p(out),
+                          ctypes.byref(acc))
+    return s, out, acc.value
+
+
+def apply_move(lig, xyz, P, q, bits=64, fp64_input=True):
+    """The refinement's local move q = (t, omega, theta) applied at (xyz, P)."""
+    lib = _load()
+    keep = _Keep()
+    L = _lig(lig, keep, fp64_input)
+    x = keep(np.asarray(xyz).reshape(-1, 3), np.float64)
+    Pp = keep(P, np.float64)
+    qq = keep(q, np.float64)
+    out = np.zeros_like(x)
+    Po = np.zeros(3)
+    lib.oracle_apply_move(ctypes.c_int(bits), ctypes.byref(L), _p(x), _p(Pp), _p(qq), _p(out), _p(Po))
+    return out, Po
+
+
+def move_grad(lig, pocket, xyz, P, bits=64, fp64_input=True):
+    lib = _load()
+    keep = _Keep()
+    g = _grid(pocket, keep)
+    L = _lig(lig, keep, fp64_input)
+    x = keep(np.asarray(xyz).reshape(-1, 3), np.float64)
+    Pp = keep(P, np.float64)
+    gr = np.zeros(6 + L.K)
+    s = lib.oracle_move_grad(ctypes.c_int(bits), ctypes.byref(g), ctypes.byref(L), _p(x), _p(Pp), _p(gr))
+    return s, gr
+
+
+def move_clash_free(lig, xyz, bits=64, fp64_input=True, clash2=None):
+    lib = _load()
+    keep = _Keep()
+    L = _lig(lig, keep, fp64_input)
+    x = keep(np.asarray(xyz).reshape(-1, 3), np.float64)
+    return bool(lib.oracle_move_clash_free(ctypes.c_int(bits), ctypes.byref(L), _p(x),
+                                           ctypes.c_double(CLASH2 if clash2 is None else clash2)))
 
 
 def topk(scores, k):

@@ -392,6 +392,193 @@ void rodrigues(const double u[3], double th, double m[9]) {
   m[6] = t * u[0] * u[2] - s * u[1]; m[7] = t * u[1] * u[2] + s * u[0]; m[8] = c + t * u[2] * u[2];
 }
 
+// ---- local move (t, omega, theta) applied to a pose: torsions deepest first
+// (k = K-1 .. 0) about the current bond axes, then the rotation by |omega|
+// about the axis omega/|omega| through the pivot, then + t (the pivot moves
+// with t).  Every rotation uses the torsion-scan matrix script with the
+// (cos, sin) of its angle; torsion axes are (x_b - x_a) * inv_len as in the scans.
+template <class R>
+void apply_move(const Lig<R>& L, Pose<R>& p, const R* q) {
+  for (int k = L.K - 1; k >= 0; --k) {
+    const R th = q[6 + k];
+    if (th == (R)0) continue;
+    rotate_torsion(L, p, k, std::cos(th), std::sin(th), p);
+  }
+  const R w2 = fma(q[5], q[5], fma(q[4], q[4], q[3] * q[3]));
+  if (w2 > (R)0) {
+    const R w = std::sqrt(w2);
+    R m[9];
+    torsion_matrix(q[3] / w, q[4] / w, q[5] / w, std::cos(w), std::sin(w), m);
+    for (size_t i = 0; i < p.X[0].size(); ++i) {
+      R v[3] = {p.X[0][i] - p.P[0], p.X[1][i] - p.P[1], p.X[2][i] - p.P[2]};
+      for (int d = 0; d < 3; ++d) {
+        R y = fma(m[3 * d + 2], v[2], fma(m[3 * d + 1], v[1], m[3 * d] * v[0]));
+        p.X[d][i] = p.P[d] + y;
+      }
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    for (size_t i = 0; i < p.X[0].size(); ++i) p.X[d][i] = p.X[d][i] + q[d];
+    p.P[d] = p.P[d] + q[d];
+  }
+}
+
+// ---- trilinear score of a pose and its gradient with respect to the local
+// move at zero (force / torque form, torsion axes (x_b - x_a) * inv_len); sums
+// in atom order.
+template <class R>
+R move_gradient(const Grid<R>& g, const Lig<R>& L, const Pose<R>& p, std::vector<R>& grad) {
+  const int N = L.N, K = L.K;
+  std::vector<R> ga((size_t)3 * N);
+  R s = (R)0;
+  for (int i = 0; i < N; ++i) s = s + trilinear(g, p.X[0][i], p.X[1][i], p.X[2][i], &ga[3 * i]);
+  grad.assign(6 + K, (R)0);
+  for (int i = 0; i < N; ++i) {
+    const R* gi = &ga[3 * i];
+    R r[3] = {p.X[0][i] - p.P[0], p.X[1][i] - p.P[1], p.X[2][i] - p.P[2]};
+    for (int d = 0; d < 3; ++d) grad[d] = grad[d] + gi[d];
+    grad[3] = grad[3] + (r[1] * gi[2] - r[2] * gi[1]);
+    grad[4] = grad[4] + (r[2] * gi[0] - r[0] * gi[2]);
+    grad[5] = grad[5] + (r[0] * gi[1] - r[1] * gi[0]);
+  }
+  for (int k = 0; k < K; ++k) {
+    const int a = L.ta[k], b = L.tb[k];
+    R u[3];
+    for (int d = 0; d < 3; ++d) u[d] = (p.X[d][b] - p.X[d][a]) * L.inv_len[k];
+    R t[3] = {(R)0, (R)0, (R)0};
+    for (int i = 0; i < N; ++i) {
+      if (!L.moves(i, k)) continue;
+      const R* gi = &ga[3 * i];
+      R r[3] = {p.X[0][i] - p.X[0][a], p.X[1][i] - p.X[1][a], p.X[2][i] - p.X[2][a]};
+      t[0] = t[0] + (r[1] * gi[2] - r[2] * gi[1]);
+      t[1] = t[1] + (r[2] * gi[0] - r[0] * gi[2]);
+      t[2] = t[2] + (r[0] * gi[1] - r[1] * gi[0]);
+    }
+    grad[6 + k] = u[0] * t[0] + u[1] * t[1] + u[2] * t[2];
+  }
+  return s;
+}
+
+// ---- intramolecular clash rule of refinement: the union over bonds of the
+// pairs a torsion can move -- (i, j) such that for some bond k exactly one of
+// them is in F_k, the moving one is not b_k and the other is not a_k -- must all
+// satisfy d^2 >= clash2.
+template <class R>
+bool move_clash_free(const Lig<R>& L, const Pose<R>& p, R clash2) {
+  for (int i = 0; i < L.N; ++i)
+    for (int j = i + 1; j < L.N; ++j) {
+      uint32_t diff = L.mask[i] ^ L.mask[j];
+      bool changes = false;
+      for (int k = 0; k < L.K && !changes; ++k) {
+        if (!((diff >> k) & 1u)) continue;
+        const int mover = L.moves(i, k) ? i : j, other = mover == i ? j : i;
+        changes = mover != L.tb[k] && other != L.ta[k];
+      }
+      if (!changes) continue;
+      R dx = p.X[0][i] - p.X[0][j], dy = p.X[1][i] - p.X[1][j], dz = p.X[2][i] - p.X[2][j];
+      if (fma(dz, dz, fma(dy, dy, dx * dx)) < clash2) return false;
+    }
+  return true;
+}
+
+// ---- local refinement: `steps` gradient-ascent steps on the trilinear score.
+// Step = (eta_t g_t, eta_w g_w, eta_th g_th) with g_t and g_w clipped to norms
+// clip_t and clip_w and every g_th component to [-clip_th, clip_th], times the
+// current step scale (initially 1).  A step whose pose breaks the clash rule is
+// rejected (pose kept) and halves the step scale.  The best-scoring pose seen,
+// the input included, is returned.
+template <class R>
+struct RefineP {
+  int steps;
+  R eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash2;
+};
+
+template <class R>
+R refine(const Grid<R>& g, const Lig<R>& L, Pose<R>& pose, const RefineP<R>& rp, int* accepted) {
+  Pose<R> best = pose;
+  R best_s = score_trilinear(g, pose);
+  R scale = (R)1;
+  int acc = 0;
+  std::vector<R> grad, q(6 + L.K);
+  for (int step = 0; step < rp.steps; ++step) {
+    move_gradient(g, L, pose, grad);
+    R dt[3], dw[3];
+    for (int d = 0; d < 3; ++d) { dt[d] = rp.eta_t * grad[d]; dw[d] = rp.eta_w * grad[3 + d]; }
+    const R nt = std::sqrt(fma(dt[2], dt[2], fma(dt[1], dt[1], dt[0] * dt[0])));
+    const R nw = std::sqrt(fma(dw[2], dw[2], fma(dw[1], dw[1], dw[0] * dw[0])));
+    const R ft = nt > rp.clip_t ? rp.clip_t / nt : (R)1;
+    const R fw = nw > rp.clip_w ? rp.clip_w / nw : (R)1;
+    for (int d = 0; d < 3; ++d) {
+      q[d] = (dt[d] * ft) * scale;
+      q[3 + d] = (dw[d] * fw) * scale;
+    }
+    for (int k = 0; k < L.K; ++k) {
+      R v = rp.eta_th * grad[6 + k];
+      v = std::min(std::max(v, -rp.clip_th), rp.clip_th);
+      q[6 + k] = v * scale;
+    }
+    Pose<R> cand = pose;
+    apply_move(L, cand, q.data());
+    if (!move_clash_free(L, cand, rp.clash2)) {
+      scale = scale * (R)0.5;
+      continue;
+    }
+    pose = cand;
+    ++acc;
+    const R s = score_trilinear(g, pose);
+    if (s > best_s) { best_s = s; best = pose; }
+  }
+  pose = best;
+  if (accepted) *accepted = acc;
+  return best_s;
+}
+
+template <class R>
+double refine_t(const og_grid* gg, const og_ligand* l, const double* P, const double* prm, double* out_xyz,
+                int* accepted) {
+  Grid<R> g(gg);
+  Lig<R> L(l);
+  Pose<R> p;
+  to_pose(L, l->xyz, P, p);
+  RefineP<R> rp{(int)prm[0], (R)prm[1], (R)prm[2], (R)prm[3], (R)prm[4], (R)prm[5], (R)prm[6], (R)prm[7]};
+  R s = refine(g, L, p, rp, accepted);
+  from_pose(p, out_xyz, (double*)nullptr);
+  return (double)s;
+}
+
+template <class R>
+int apply_move_t(const og_ligand* l, const double* xyz, const double* P, const double* q, double* out_xyz,
+                 double* out_P) {
+  Lig<R> L(l);
+  Pose<R> p;
+  to_pose(L, xyz, P, p);
+  std::vector<R> qq(6 + L.K);
+  for (int i = 0; i < 6 + L.K; ++i) qq[i] = (R)q[i];
+  apply_move(L, p, qq.data());
+  from_pose(p, out_xyz, out_P);
+  return 0;
+}
+
+template <class R>
+double move_grad_t(const og_grid* gg, const og_ligand* l, const double* xyz, const double* P, double* grad) {
+  Grid<R> g(gg);
+  Lig<R> L(l);
+  Pose<R> p;
+  to_pose(L, xyz, P, p);
+  std::vector<R> gr;
+  R s = move_gradient(g, L, p, gr);
+  for (int i = 0; i < 6 + L.K; ++i) grad[i] = (double)gr[i];
+  return (double)s;
+}
+
+template <class R>
+int move_clash_free_t(const og_ligand* l, const double* xyz, double clash2) {
+  Lig<R> L(l);
+  Pose<R> p;
+  to_pose(L, xyz, (const double*)nullptr, p);
+  return move_clash_free(L, p, (R)clash2) ? 1 : 0;
+}
+
 }  // namespace
 
 // Dock one ligand: all restarts; final trilinear score per restart; optional
@@ -552,3 +739,31 @@ extern "C" int oracle_topk(int R, const double* scores, int k, int32_t* out_idx)
   return 0;
 }
 
+
+// Local refinement of one pose (xyz, pivot P).  prm = (steps, eta_t, eta_w,
+// eta_th, clip_t, clip_w, clip_th, clash2).  Returns the best score; out_xyz
+// receives the best pose; *accepted the number of accepted steps.
+extern "C" double oracle_refine(int real_bits, const og_grid* g, const og_ligand* l, const double* P,
+                                const double* prm, double* out_xyz, int* accepted) {
+  return real_bits == 32 ? refine_t<float>(g, l, P, prm, out_xyz, accepted)
+                         : refine_t<double>(g, l, P, prm, out_xyz, accepted);
+}
+
+// The local move q = (t, omega, theta) applied to a pose (as refinement applies it).
+extern "C" int oracle_apply_move(int real_bits, const og_ligand* l, const double* xyz, const double* P,
+                                 const double* q, double* out_xyz, double* out_P) {
+  return real_bits == 32 ? apply_move_t<float>(l, xyz, P, q, out_xyz, out_P)
+                         : apply_move_t<double>(l, xyz, P, q, out_xyz, out_P);
+}
+
+// Trilinear score and gradient with respect to the local move at zero, as
+// refinement computes it (axes from inv_len, sums in atom order).
+extern "C" double oracle_move_grad(int real_bits, const og_grid* g, const og_ligand* l, const double* xyz,
+                                   const double* P, double* grad) {
+  return real_bits == 32 ? move_grad_t<float>(g, l, xyz, P, grad) : move_grad_t<double>(g, l, xyz, P, grad);
+}
+
+// 1 if the pose satisfies refinement's clash rule.
+extern "C" int oracle_move_clash_free(int real_bits, const og_ligand* l, const double* xyz, double clash2) {
+  return real_bits == 32 ? move_clash_free_t<float>(l, xyz, clash2) : move_clash_free_t<double>(l, xyz, clash2);
+}
