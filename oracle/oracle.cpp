@@ -392,6 +392,35 @@ void rodrigues(const double u[3], double th, double m[9]) {
   m[6] = t * u[0] * u[2] - s * u[1]; m[7] = t * u[1] * u[2] + s * u[0]; m[8] = c + t * u[2] * u[2];
 }
 
+// ---- (cos x, sin x) of a refinement step angle.  Steps are clipped to at most
+// pi/4, where the Taylor series to x^13 / x^12 (Horner in x^2, fma) is accurate to
+// well below an FP32 ulp; the same polynomial is the arithmetic contract of
+// refinement in both precisions.  Larger angles (only reachable through
+// apply_move called directly) use the library functions.
+template <class R>
+void step_cos_sin(R x, R& c, R& s) {
+  if (!(std::fabs(x) <= (R)0.7853981633974483)) {
+    c = std::cos(x);
+    s = std::sin(x);
+    return;
+  }
+  const R x2 = x * x;
+  R ps = (R)(1.0 / 6227020800.0);
+  ps = fma(ps, x2, (R)(-1.0 / 39916800.0));
+  ps = fma(ps, x2, (R)(1.0 / 362880.0));
+  ps = fma(ps, x2, (R)(-1.0 / 5040.0));
+  ps = fma(ps, x2, (R)(1.0 / 120.0));
+  ps = fma(ps, x2, (R)(-1.0 / 6.0));
+  s = fma(x * x2, ps, x);
+  R pc = (R)(1.0 / 479001600.0);
+  pc = fma(pc, x2, (R)(-1.0 / 3628800.0));
+  pc = fma(pc, x2, (R)(1.0 / 40320.0));
+  pc = fma(pc, x2, (R)(-1.0 / 720.0));
+  pc = fma(pc, x2, (R)(1.0 / 24.0));
+  pc = fma(pc, x2, (R)(-0.5));
+  c = fma(x2, pc, (R)1);
+}
+
 // ---- local move (t, omega, theta) applied to a pose: torsions deepest first
 // (k = K-1 .. 0) about the current bond axes, then the rotation by |omega|
 // about the axis omega/|omega| through the pivot, then + t (the pivot moves
@@ -402,13 +431,16 @@ void apply_move(const Lig<R>& L, Pose<R>& p, const R* q) {
   for (int k = L.K - 1; k >= 0; --k) {
     const R th = q[6 + k];
     if (th == (R)0) continue;
-    rotate_torsion(L, p, k, std::cos(th), std::sin(th), p);
+    R c, sn;
+    step_cos_sin(th, c, sn);
+    rotate_torsion(L, p, k, c, sn, p);
   }
   const R w2 = fma(q[5], q[5], fma(q[4], q[4], q[3] * q[3]));
   if (w2 > (R)0) {
     const R w = std::sqrt(w2);
-    R m[9];
-    torsion_matrix(q[3] / w, q[4] / w, q[5] / w, std::cos(w), std::sin(w), m);
+    R m[9], c, sn;
+    step_cos_sin(w, c, sn);
+    torsion_matrix(q[3] / w, q[4] / w, q[5] / w, c, sn, m);
     for (size_t i = 0; i < p.X[0].size(); ++i) {
       R v[3] = {p.X[0][i] - p.P[0], p.X[1][i] - p.P[1], p.X[2][i] - p.P[2]};
       for (int d = 0; d < 3; ++d) {
