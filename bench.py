@@ -102,7 +102,7 @@ def read_traffic(kernel_tag):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("dock.hip", "lg_internal.h"):
+    for f in ("dock.hip", "lg_internal.h", "lg_device.h"):
         h.update(open(os.path.join(ROOT, "paper_2303_06150_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -293,9 +293,11 @@ def main():
         log(f"one-bucket ablation: {nab / abl_s:.1f} ligands/s vs bucketed {nab / buck_ab_s:.1f} on {nab}")
 
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB (a device-to-device
+        # copy_ would go to the DMA engines and not show up as a kernel)
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload

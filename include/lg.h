@@ -167,10 +167,15 @@ lg_status lg_dock_batch(lg_pocket pocket, const lg_ligands* ligands, const lg_do
  * theta[K]) at zero for the local move (torsions about the current bond axes,
  * rotation omega about ref_point, translation t), i.e. sum g, sum (x-P) x g,
  * u_k . sum_{F_k} (x - x_{a_k}) x g with g the trilinear gradient and u_k the
- * unit bond axis.  top_m > 0: top_idx / top_score (device [top_m]) receive the
- * global ranking (score descending, equal scores: lower index). */
-lg_status lg_score(lg_pocket pocket, const lg_ligands* poses, int32_t interp, float* score, float* grad,
-                   int32_t top_m, int32_t* top_idx, float* top_score, void* stream);
+ * unit bond axis.  moves (optional, trilinear only, same layout as grad): each
+ * pose is first moved by its local parameters q = (t, omega, theta) --
+ * torsions deepest first about the current bond axes, rotation by |omega| about
+ * omega/|omega| through ref_point, translation (pivot included) -- then scored;
+ * grad is then d(score)/dq at q (the omega part through the transposed left
+ * Jacobian of SO(3)).  top_m > 0: top_idx / top_score (device [top_m]) receive
+ * the global ranking (score descending, equal scores: lower index). */
+lg_status lg_score(lg_pocket pocket, const lg_ligands* poses, int32_t interp, const float* moves, float* score,
+                   float* grad, int32_t top_m, int32_t* top_idx, float* top_score, void* stream);
 
 /* Local refinement of poses by gradient ascent on the trilinear score.  Each
  * step: gradient at the current pose, step = (eta_t*g_t, eta_w*g_w,

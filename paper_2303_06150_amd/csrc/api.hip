@@ -33,6 +33,17 @@ hipError_t launch_brick(const float* padded, int px, int py, int pz, int nbx, in
 hipError_t launch_bucketing(const int32_t* atom_offset, const int32_t* tors_offset, int n, const ClusterBounds& cb,
                             int32_t* cls, int32_t* counts, int32_t* start, int32_t* fill, int32_t* perm,
                             int32_t* cursors, hipStream_t st);
+struct RefineDev {
+  int steps;
+  float eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash2;
+  float* xo;
+  float* yo;
+  float* zo;
+  float* score;
+};
+hipError_t launch_refine(int nslot, const GridDev& G, const LigDev& P, const RefineDev& Rp, int n, hipStream_t st);
+hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, const float* moves, int n, float* score,
+                              float* grad, hipStream_t st);
 hipError_t launch_check(const int32_t* atom_offset, const int32_t* tors_offset, const int32_t* tors_atoms, int n,
                         int total_atoms, int total_tors, int32_t* stats, hipStream_t st);
 }  // namespace lg
@@ -592,13 +603,13 @@ int32_t lg_bucket_stats(lg_pocket p, lg_bucket_stat* out, int32_t capacity) {
   return nl;
 }
 
-lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, float* score, float* grad, int32_t top_m,
-                   int32_t* top_idx, float* top_score, void* stream) {
+lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, const float* moves, float* score, float* grad,
+                   int32_t top_m, int32_t* top_idx, float* top_score, void* stream) {
   if (!p) return fail(LG_ERR_INVALID_ARG, "pocket is NULL");
-  lg_status s = check_ligands(L, grad != nullptr);
+  lg_status s = check_ligands(L, grad != nullptr || moves != nullptr);
   if (s != LG_OK) return s;
   if (interp != LG_NEAREST && interp != LG_TRILINEAR) return fail(LG_ERR_INVALID_ARG, "interp must be LG_NEAREST or LG_TRILINEAR");
-  if (grad && interp != LG_TRILINEAR) return fail(LG_ERR_INVALID_ARG, "gradients need LG_TRILINEAR");
+  if ((grad || moves) && interp != LG_TRILINEAR) return fail(LG_ERR_INVALID_ARG, "gradients and moves need LG_TRILINEAR");
   if (L->n > 0 && !score) return fail(LG_ERR_INVALID_ARG, "score is NULL");
   if (top_m < 0 || top_m > L->n) return fail(LG_ERR_INVALID_ARG, "top_m %d outside 0..n", top_m);
   if (top_m > 0 && (!top_idx || !top_score)) return fail(LG_ERR_INVALID_ARG, "top_idx and top_score are required for top_m > 0");
@@ -623,7 +634,10 @@ lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, float* scor
   int max_atoms = 0, max_tors = 0;
   s = check_on_device(p, L, (int32_t*)(ws + o_stats), st, &max_atoms, &max_tors);
   if (s != LG_OK) return s;
-  LG_HIP(lg::launch_score(p->grid, lig_dev(L), n, interp, score, grad, st));
+  if (moves)
+    LG_HIP(lg::launch_score_moves((max_atoms + 63) / 64, p->grid, lig_dev(L), moves, n, score, grad, st));
+  else
+    LG_HIP(lg::launch_score(p->grid, lig_dev(L), n, interp, score, grad, st));
   if (top_m > 0) {
     float* k0 = (float*)(ws + o_k0);
     float* k1 = (float*)(ws + o_k1);
@@ -637,10 +651,36 @@ lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, float* scor
   return LG_OK;
 }
 
-lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* params, float* x_out, float* y_out,
+lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp, float* x_out, float* y_out,
                     float* z_out, float* score_out, void* stream) {
-  (void)p; (void)L; (void)params; (void)x_out; (void)y_out; (void)z_out; (void)score_out; (void)stream;
-  return fail(LG_ERR_UNSUPPORTED, "lg_refine is not available in this build");
+  if (!p || !rp) return fail(LG_ERR_INVALID_ARG, "pocket and params must not be NULL");
+  lg_status s = check_ligands(L, true);
+  if (s != LG_OK) return s;
+  if (rp->steps < 0 || rp->steps > 100000) return fail(LG_ERR_LIMIT, "steps %d outside 0..100000", rp->steps);
+  const float quarter = 0.78539816f;
+  if (!std::isfinite(rp->eta_t) || !std::isfinite(rp->eta_w) || !std::isfinite(rp->eta_th) ||
+      !std::isfinite(rp->clash_dist2) || !(rp->clip_t > 0.f) || !std::isfinite(rp->clip_t) ||
+      !(rp->clip_w > 0.f) || rp->clip_w > quarter || !(rp->clip_th > 0.f) || rp->clip_th > quarter)
+    return fail(LG_ERR_INVALID_ARG, "steps need finite etas, clip_t > 0 and rotation clips in (0, pi/4]");
+  if (L->n > 0 && (!x_out || !y_out || !z_out || !score_out)) return fail(LG_ERR_INVALID_ARG, "outputs are required");
+  if (L->n == 0) return LG_OK;
+  hipStream_t st = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+  Layout lay;
+  const size_t o_stats = lay.take(16 * sizeof(int32_t));
+  s = ensure_ws(p, lay.off);
+  if (s != LG_OK) return s;
+  int max_atoms = 0, max_tors = 0;
+  s = check_on_device(p, L, (int32_t*)((char*)p->ws + o_stats), st, &max_atoms, &max_tors);
+  if (s != LG_OK) return s;
+  lg::RefineDev R;
+  R.steps = rp->steps;
+  R.eta_t = rp->eta_t; R.eta_w = rp->eta_w; R.eta_th = rp->eta_th;
+  R.clip_t = rp->clip_t; R.clip_w = rp->clip_w; R.clip_th = rp->clip_th;
+  R.clash2 = rp->clash_dist2;
+  R.xo = x_out; R.yo = y_out; R.zo = z_out; R.score = score_out;
+  LG_HIP(lg::launch_refine((max_atoms + 63) / 64, p->grid, lig_dev(L), R, L->n, st));
+  return LG_OK;
 }
 
 }  // extern "C"

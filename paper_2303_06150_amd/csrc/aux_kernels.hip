@@ -1,56 +1,13 @@
 // Pose scoring (nearest / trilinear + force-torque adjoint), pocket padding,
 // device-side input preparation (classify / scan / scatter into size buckets)
 // and validation kernels.
-#include "lg_internal.h"
+#include "lg_device.h"
 
 #include <climits>
 
 namespace lg {
 
-__device__ __forceinline__ float nearest_s(const GridDev& G, float x, float y, float z) {
-  int ix = clamp_node(fmaf(x, G.inv_h, G.c0[0]), G.fn[0]);
-  int iy = clamp_node(fmaf(y, G.inv_h, G.c0[1]), G.fn[1]);
-  int iz = clamp_node(fmaf(z, G.inv_h, G.c0[2]), G.fn[2]);
-  return G.g0[ix + iy * G.stride[1] + iz * G.stride[2]];
-}
 
-__device__ __forceinline__ float trilinear_s(const GridDev& G, float x, float y, float z, float* g) {
-  float f0 = (x - G.o[0]) * G.inv_h, f1 = (y - G.o[1]) * G.inv_h, f2 = (z - G.o[2]) * G.inv_h;
-  bool in = f0 >= 0.f && f0 < G.fn1[0] && f1 >= 0.f && f1 < G.fn1[1] && f2 >= 0.f && f2 < G.fn1[2];
-  if (!in) {
-    g[0] = g[1] = g[2] = 0.f;
-    return G.out;
-  }
-  int i0 = (int)f0, i1 = (int)f1, i2 = (int)f2;
-  float w0 = f0 - (float)i0, w1 = f1 - (float)i1, w2 = f2 - (float)i2;
-  const int s1 = G.stride[1], s2 = G.stride[2];
-  const float* p = G.g0 + i0 + i1 * s1 + i2 * s2;
-  float c000 = p[0], c100 = p[1], c010 = p[s1], c110 = p[s1 + 1];
-  float c001 = p[s2], c101 = p[s2 + 1], c011 = p[s2 + s1], c111 = p[s2 + s1 + 1];
-  float c00 = fmaf(w0, c100 - c000, c000), c10 = fmaf(w0, c110 - c010, c010);
-  float c01 = fmaf(w0, c101 - c001, c001), c11 = fmaf(w0, c111 - c011, c011);
-  float c0 = fmaf(w1, c10 - c00, c00), c1 = fmaf(w1, c11 - c01, c01);
-  float e00 = c100 - c000, e10 = c110 - c010, e01 = c101 - c001, e11 = c111 - c011;
-  float e0 = fmaf(w1, e10 - e00, e00), e1 = fmaf(w1, e11 - e01, e01);
-  g[0] = fmaf(w2, e1 - e0, e0) * G.inv_h;
-  float d0 = c10 - c00, d1 = c11 - c01;
-  g[1] = fmaf(w2, d1 - d0, d0) * G.inv_h;
-  g[2] = (c1 - c0) * G.inv_h;
-  return fmaf(w2, c1 - c0, c0);
-}
-
-template <int NSLOT>
-__device__ __forceinline__ float atom_value_s(const float (&v)[NSLOT], int a) {
-  // one readlane per slot, selected on the scalar side (no dynamic register index)
-  const int slot = a >> 6, l = a & 63;
-  int r = __builtin_amdgcn_readlane(__float_as_int(v[0]), l);
-#pragma unroll
-  for (int s = 1; s < NSLOT; ++s) {
-    const int rs = __builtin_amdgcn_readlane(__float_as_int(v[s]), l);
-    r = slot == s ? rs : r;
-  }
-  return __int_as_float(r);
-}
 
 // One wavefront per pose: score = sum over atoms in atom order; optional
 // gradient with respect to (t, omega, theta) at zero (force / torque form).
@@ -74,7 +31,7 @@ __global__ __launch_bounds__(256) void score_kernel(GridDev G, LigDev P, int n, 
     mk[s] = in ? P.mask[abase + a] : 0u;
     float gg[3] = {0.f, 0.f, 0.f};
     v[s] = 0.f;
-    if (in) v[s] = interp == LG_TRILINEAR ? trilinear_s(G, x[0][s], x[1][s], x[2][s], gg) : nearest_s(G, x[0][s], x[1][s], x[2][s]);
+    if (in) v[s] = interp == LG_TRILINEAR ? trilinear(G, x[0][s], x[1][s], x[2][s], gg) : nearest(G, x[0][s], x[1][s], x[2][s]);
     g[0][s] = gg[0]; g[1][s] = gg[1]; g[2][s] = gg[2];
   }
   float total = 0.f;
@@ -105,8 +62,8 @@ __global__ __launch_bounds__(256) void score_kernel(GridDev G, LigDev P, int n, 
   for (int k = 0; k < K; ++k) {
     const int a = __builtin_amdgcn_readfirstlane(P.tors_atoms[2 * (toff + k)]);
     const int b = __builtin_amdgcn_readfirstlane(P.tors_atoms[2 * (toff + k) + 1]);
-    const float xa = atom_value_s(x[0], a), ya = atom_value_s(x[1], a), za = atom_value_s(x[2], a);
-    float ux = atom_value_s(x[0], b) - xa, uy = atom_value_s(x[1], b) - ya, uz = atom_value_s(x[2], b) - za;
+    const float xa = atom_value(x[0], a), ya = atom_value(x[1], a), za = atom_value(x[2], a);
+    float ux = atom_value(x[0], b) - xa, uy = atom_value(x[1], b) - ya, uz = atom_value(x[2], b) - za;
     const float inv = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
     ux *= inv; uy *= inv; uz *= inv;
     float t[3] = {0.f, 0.f, 0.f};

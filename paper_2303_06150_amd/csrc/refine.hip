@@ -1,0 +1,380 @@
+// Local refinement of poses on the trilinear grid (gradient ascent in the local
+// parameters t, omega, theta) and the local move applied before scoring.
+//
+// One wavefront refines one pose; atom 64 s + lane sits in slot s.  Each step:
+// trilinear values and gradients per atom, force / torque / per-bond torque
+// sums in atom order (readlane), the clipped step, the local move (torsions
+// deepest first about the current bond axes, rotation about the pivot,
+// translation), the intramolecular clash rule over every pair a torsion can
+// move, accept (keep the best pose) or reject (halve the step scale).  The
+// arithmetic is the CPU reference's FP32 script: sums in atom order, (cos, sin)
+// of step angles from one fixed polynomial, correctly rounded sqrt and divide.
+#include "lg_device.h"
+
+namespace lg {
+
+struct RefineDev {
+  int steps;
+  float eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash2;
+  float* xo;
+  float* yo;
+  float* zo;
+  float* score;
+};
+
+template <int NSLOT>
+struct MoveState {
+  float x[3][NSLOT];
+  float piv[3];
+};
+
+// (cos, sin) of a move angle: the step polynomial inside refinement (angles
+// clipped to pi/4), the library functions for arbitrary moves.
+template <bool LIB>
+__device__ __forceinline__ void move_cos_sin(float x, float& c, float& s) {
+  if (LIB) {
+    sincosf(x, &s, &c);
+  } else {
+    step_cos_sin(x, c, s);
+  }
+}
+
+// Torsions deepest first, then rotation by |w| about w/|w| through the pivot,
+// then + t (pivot included).  q holds t[3], w[3]; th the bond angles.
+template <int NSLOT, bool LIB = false>
+__device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
+                           const float* inv_len, const float* q, const float* th) {
+  const int lane = lane_id();
+  for (int k = K - 1; k >= 0; --k) {
+    const float ang = th[k];
+    if (ang == 0.f) continue;
+    float c, s;
+    move_cos_sin<LIB>(ang, c, s);
+    const int a = tors[k].x, b = tors[k].y;
+    const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
+    const float il = inv_len[k];
+    const float ux = (atom_value(p.x[0], b) - xa) * il, uy = (atom_value(p.x[1], b) - ya) * il,
+                uz = (atom_value(p.x[2], b) - za) * il;
+    float m[9];
+    torsion_matrix(ux, uy, uz, c, s, m);
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      const int at = sl * 64 + lane;
+      if (at < N && ((mk[sl] >> k) & 1u) && at != b) {
+        float y0, y1, y2;
+        mat_apply(m, p.x[0][sl] - xa, p.x[1][sl] - ya, p.x[2][sl] - za, y0, y1, y2);
+        p.x[0][sl] = xa + y0;
+        p.x[1][sl] = ya + y1;
+        p.x[2][sl] = za + y2;
+      }
+    }
+  }
+  const float w2 = fmaf(q[5], q[5], fmaf(q[4], q[4], q[3] * q[3]));
+  if (w2 > 0.f) {
+    const float w = sqrtf(w2);
+    float c, s, m[9];
+    move_cos_sin<LIB>(w, c, s);
+    torsion_matrix(q[3] / w, q[4] / w, q[5] / w, c, s, m);
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      float y0, y1, y2;
+      mat_apply(m, p.x[0][sl] - p.piv[0], p.x[1][sl] - p.piv[1], p.x[2][sl] - p.piv[2], y0, y1, y2);
+      p.x[0][sl] = p.piv[0] + y0;
+      p.x[1][sl] = p.piv[1] + y1;
+      p.x[2][sl] = p.piv[2] + y2;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) p.x[d][sl] = p.x[d][sl] + q[d];
+    p.piv[d] = p.piv[d] + q[d];
+  }
+}
+
+// Trilinear score and its gradient with respect to the local move at zero;
+// sums in atom order.  g_out: t[3], w[3], then theta[K] into th_grad.
+template <int NSLOT>
+__device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N,
+                               int K, const int2* tors, const float* inv_len, float* g_out, float* th_grad) {
+  const int lane = lane_id();
+  float v[NSLOT], g[3][NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    float gg[3] = {0.f, 0.f, 0.f};
+    v[s] = (s * 64 + lane < N) ? trilinear(G, p.x[0][s], p.x[1][s], p.x[2][s], gg) : 0.f;
+    g[0][s] = gg[0]; g[1][s] = gg[1]; g[2][s] = gg[2];
+  }
+  const float score = atom_order_sum(v, N);
+  float tq[3][NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const float r0 = p.x[0][s] - p.piv[0], r1 = p.x[1][s] - p.piv[1], r2 = p.x[2][s] - p.piv[2];
+    tq[0][s] = r1 * g[2][s] - r2 * g[1][s];
+    tq[1][s] = r2 * g[0][s] - r0 * g[2][s];
+    tq[2][s] = r0 * g[1][s] - r1 * g[0][s];
+  }
+  for (int d = 0; d < 3; ++d) {
+    g_out[d] = atom_order_sum(g[d], N);
+    g_out[3 + d] = atom_order_sum(tq[d], N);
+  }
+  for (int k = 0; k < K; ++k) {
+    const int a = tors[k].x, b = tors[k].y;
+    const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
+    const float il = inv_len[k];
+    const float ux = (atom_value(p.x[0], b) - xa) * il, uy = (atom_value(p.x[1], b) - ya) * il,
+                uz = (atom_value(p.x[2], b) - za) * il;
+    float t[3][NSLOT];
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const bool in = (mk[s] >> k) & 1u;
+      const float r0 = p.x[0][s] - xa, r1 = p.x[1][s] - ya, r2 = p.x[2][s] - za;
+      t[0][s] = in ? r1 * g[2][s] - r2 * g[1][s] : 0.f;
+      t[1][s] = in ? r2 * g[0][s] - r0 * g[2][s] : 0.f;
+      t[2][s] = in ? r0 * g[1][s] - r1 * g[0][s] : 0.f;
+    }
+    const float t0 = atom_order_sum(t[0], N), t1 = atom_order_sum(t[1], N), t2 = atom_order_sum(t[2], N);
+    if (lane == 0) th_grad[k] = ux * t0 + uy * t1 + uz * t2;
+  }
+  return score;
+}
+
+// Refinement clash rule: every pair that some bond's torsion moves -- exactly one
+// of the two in F_k, the moving one not b_k, the other not a_k -- at squared
+// distance >= clash2.  `pos` holds the pose (xyz, mask bits in w) in LDS.
+template <int NSLOT>
+__device__ bool move_clash_free(const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N,
+                                const int2* tors, const float4* pos, float clash2) {
+  const int lane = lane_id();
+  bool clash = false;
+  for (int j = 0; j < N; ++j) {
+    const float4 pj = pos[j];
+    const uint32_t mj = __float_as_uint(pj.w);
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const int i = s * 64 + lane;
+      const uint32_t diff = mk[s] ^ mj;
+      if (i >= N || j <= i || diff == 0u) continue;
+      bool changes = false;
+      for (uint32_t d = diff; d != 0u && !changes; d &= d - 1u) {
+        const int k = __builtin_ctz(d);
+        const int mover = ((mk[s] >> k) & 1u) ? i : j;
+        const int other = mover == i ? j : i;
+        changes = mover != tors[k].y && other != tors[k].x;
+      }
+      if (!changes) continue;
+      const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
+      if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2) clash = true;
+    }
+  }
+  return !wave_any(clash);
+}
+
+template <int NSLOT>
+__global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, RefineDev Rp, int n) {
+  extern __shared__ float4 lds[];
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
+  float4* pos = lds + (size_t)wave * (64 * NSLOT + 32);
+  int2* tors = reinterpret_cast<int2*>(pos + 64 * NSLOT);     // 32 entries (16 float4)
+  float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries (8 float4)
+  float* th = inv_len + 32;                                   // 32 bond gradients / steps (8 float4)
+  const int i = blockIdx.x * nwaves + wave;
+  if (i >= n) return;
+  const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[i]);
+  const int N = __builtin_amdgcn_readfirstlane(P.atom_offset[i + 1]) - abase;
+  const int toff = __builtin_amdgcn_readfirstlane(P.tors_offset[i]);
+  const int K = __builtin_amdgcn_readfirstlane(P.tors_offset[i + 1]) - toff;
+  if (lane < K) {
+    tors[lane] = make_int2(P.tors_atoms[2 * (toff + lane)], P.tors_atoms[2 * (toff + lane) + 1]);
+    inv_len[lane] = P.inv_len[toff + lane];
+  }
+  MoveState<NSLOT> cur, best;
+  uint32_t mk[NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    const bool in = a < N;
+    cur.x[0][s] = in ? P.x[abase + a] : 0.f;
+    cur.x[1][s] = in ? P.y[abase + a] : 0.f;
+    cur.x[2][s] = in ? P.z[abase + a] : 0.f;
+    mk[s] = in ? P.mask[abase + a] : 0u;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cur.piv[d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.ref[3 * i + d])));
+  wave_sync();
+  best = cur;
+  float v[NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) v[s] = (s * 64 + lane < N) ? trilinear(G, cur.x[0][s], cur.x[1][s], cur.x[2][s], nullptr) : 0.f;
+  float best_s = atom_order_sum(v, N);
+  float scale = 1.f;
+  float g[6];
+  for (int step = 0; step < Rp.steps; ++step) {
+    move_gradient(G, cur, mk, N, K, tors, inv_len, g, th);
+    wave_sync();
+    float q[6];
+    float dt[3], dw[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { dt[d] = Rp.eta_t * g[d]; dw[d] = Rp.eta_w * g[3 + d]; }
+    const float nt = sqrtf(fmaf(dt[2], dt[2], fmaf(dt[1], dt[1], dt[0] * dt[0])));
+    const float nw = sqrtf(fmaf(dw[2], dw[2], fmaf(dw[1], dw[1], dw[0] * dw[0])));
+    const float ft = nt > Rp.clip_t ? Rp.clip_t / nt : 1.f;
+    const float fw = nw > Rp.clip_w ? Rp.clip_w / nw : 1.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      q[d] = (dt[d] * ft) * scale;
+      q[3 + d] = (dw[d] * fw) * scale;
+    }
+    for (int k = 0; k < K; ++k) {
+      float t = Rp.eta_th * th[k];
+      t = fminf(fmaxf(t, -Rp.clip_th), Rp.clip_th);
+      if (lane == 0) th[k] = t * scale;
+    }
+    wave_sync();
+    MoveState<NSLOT> cand = cur;
+    apply_move(cand, mk, N, K, tors, inv_len, q, th);
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      if (s * 64 + lane < N) pos[s * 64 + lane] = make_float4(cand.x[0][s], cand.x[1][s], cand.x[2][s], __uint_as_float(mk[s]));
+    wave_sync();
+    const bool ok = move_clash_free(cand, mk, N, tors, pos, Rp.clash2);
+    wave_sync();
+    if (!ok) {
+      scale = scale * 0.5f;
+      continue;
+    }
+    cur = cand;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) v[s] = (s * 64 + lane < N) ? trilinear(G, cur.x[0][s], cur.x[1][s], cur.x[2][s], nullptr) : 0.f;
+    const float sc = atom_order_sum(v, N);
+    if (sc > best_s) {
+      best_s = sc;
+      best = cur;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    if (a < N) {
+      Rp.xo[abase + a] = best.x[0][s];
+      Rp.yo[abase + a] = best.x[1][s];
+      Rp.zo[abase + a] = best.x[2][s];
+    }
+  }
+  if (lane == 0) Rp.score[i] = best_s;
+}
+
+// Score of poses moved by given local parameters, and the gradient with respect
+// to those parameters: each pose i is moved by q_i = (t, w, theta) (layout of
+// lg_score's gradient: 6 i + tors_offset[i]), scored (trilinear, atom order) and
+// differentiated.  d/dt and d/dtheta are the force / torque form at the moved
+// pose (later moves carry each fragment and its axis rigidly); d/dw is the
+// torque about the moved pivot times the transposed left Jacobian of SO(3):
+// J^T = I - a [w]x + b [w]x^2, a = (1 - cos|w|)/|w|^2, b = (|w| - sin|w|)/|w|^3.
+template <int NSLOT>
+__global__ __launch_bounds__(256) void score_moves_kernel(GridDev G, LigDev P, const float* moves, int n,
+                                                          float* score, float* grad) {
+  extern __shared__ float4 lds[];
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
+  float4* base = lds + (size_t)wave * 32;
+  int2* tors = reinterpret_cast<int2*>(base);                 // 32 entries
+  float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries
+  float* th = inv_len + 32;                                   // 32 entries
+  const int i = blockIdx.x * nwaves + wave;
+  if (i >= n) return;
+  const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[i]);
+  const int N = __builtin_amdgcn_readfirstlane(P.atom_offset[i + 1]) - abase;
+  const int toff = __builtin_amdgcn_readfirstlane(P.tors_offset[i]);
+  const int K = __builtin_amdgcn_readfirstlane(P.tors_offset[i + 1]) - toff;
+  const float* q_i = moves + 6 * (size_t)i + toff;
+  if (lane < K) {
+    tors[lane] = make_int2(P.tors_atoms[2 * (toff + lane)], P.tors_atoms[2 * (toff + lane) + 1]);
+    inv_len[lane] = P.inv_len[toff + lane];
+    th[lane] = q_i[6 + lane];
+  }
+  float q[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) q[d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(q_i[d])));
+  MoveState<NSLOT> p;
+  uint32_t mk[NSLOT];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    const bool in = a < N;
+    p.x[0][s] = in ? P.x[abase + a] : 0.f;
+    p.x[1][s] = in ? P.y[abase + a] : 0.f;
+    p.x[2][s] = in ? P.z[abase + a] : 0.f;
+    mk[s] = in ? P.mask[abase + a] : 0u;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) p.piv[d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.ref[3 * i + d])));
+  wave_sync();
+  apply_move<NSLOT, true>(p, mk, N, K, tors, inv_len, q, th);
+  float g[6];
+  wave_sync();
+  const float sc = move_gradient(G, p, mk, N, K, tors, inv_len, g, th);
+  wave_sync();
+  if (lane == 0) score[i] = sc;
+  if (!grad) return;
+  // transposed left Jacobian applied to the torque
+  const float w2 = fmaf(q[5], q[5], fmaf(q[4], q[4], q[3] * q[3]));
+  float a, b;
+  if (w2 < 1e-8f) {
+    a = 0.5f - w2 / 24.f;
+    b = 1.f / 6.f - w2 / 120.f;
+  } else {
+    const float w = sqrtf(w2);
+    float sn, cs;
+    sincosf(w, &sn, &cs);
+    a = (1.f - cs) / w2;
+    b = (w - sn) / (w2 * w);
+  }
+  const float tx = g[3], ty = g[4], tz = g[5];
+  // [w]x t = w x t ; [w]x^2 t = w x (w x t)
+  const float c1x = q[4] * tz - q[5] * ty, c1y = q[5] * tx - q[3] * tz, c1z = q[3] * ty - q[4] * tx;
+  const float c2x = q[4] * c1z - q[5] * c1y, c2y = q[5] * c1x - q[3] * c1z, c2z = q[3] * c1y - q[4] * c1x;
+  float* out = grad + 6 * (size_t)i + toff;
+  if (lane == 0) {
+    out[0] = g[0];
+    out[1] = g[1];
+    out[2] = g[2];
+    out[3] = tx - a * c1x + b * c2x;
+    out[4] = ty - a * c1y + b * c2y;
+    out[5] = tz - a * c1z + b * c2z;
+  }
+  if (lane < K) out[6 + lane] = th[lane];
+}
+
+hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, const float* moves, int n, float* score,
+                              float* grad, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int wpb = 4;
+  const dim3 grid((n + wpb - 1) / wpb), block(64 * wpb);
+  const size_t lds = (size_t)wpb * 32 * sizeof(float4);
+  switch (nslot) {
+    case 1: hipLaunchKernelGGL(score_moves_kernel<1>, grid, block, lds, st, G, P, moves, n, score, grad); break;
+    case 2: hipLaunchKernelGGL(score_moves_kernel<2>, grid, block, lds, st, G, P, moves, n, score, grad); break;
+    case 3: hipLaunchKernelGGL(score_moves_kernel<3>, grid, block, lds, st, G, P, moves, n, score, grad); break;
+    case 4: hipLaunchKernelGGL(score_moves_kernel<4>, grid, block, lds, st, G, P, moves, n, score, grad); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static size_t refine_lds(int nslot, int wpb) { return (size_t)wpb * (64 * nslot + 32) * sizeof(float4); }
+
+hipError_t launch_refine(int nslot, const GridDev& G, const LigDev& P, const RefineDev& Rp, int n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int wpb = 4;
+  const dim3 grid((n + wpb - 1) / wpb), block(64 * wpb);
+  switch (nslot) {
+    case 1: hipLaunchKernelGGL(refine_kernel<1>, grid, block, refine_lds(1, wpb), st, G, P, Rp, n); break;
+    case 2: hipLaunchKernelGGL(refine_kernel<2>, grid, block, refine_lds(2, wpb), st, G, P, Rp, n); break;
+    case 3: hipLaunchKernelGGL(refine_kernel<3>, grid, block, refine_lds(3, wpb), st, G, P, Rp, n); break;
+    case 4: hipLaunchKernelGGL(refine_kernel<4>, grid, block, refine_lds(4, wpb), st, G, P, Rp, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lg

@@ -99,8 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.lg_load_pocket.argtypes = [P(lg_pocket_desc), c_void_p, c_int32, c_void_p, P(c_void_p)]
     lib.lg_free_pocket.argtypes = [c_void_p]
     lib.lg_dock_batch.argtypes = [c_void_p, P(lg_ligands), P(lg_dock_params), P(lg_dock_out), c_void_p]
-    lib.lg_score.argtypes = [c_void_p, P(lg_ligands), c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
-                             c_void_p]
+    lib.lg_score.argtypes = [c_void_p, P(lg_ligands), c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                             c_void_p, c_void_p]
     lib.lg_refine.argtypes = [c_void_p, P(lg_ligands), P(lg_refine_params), c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]
     lib.lg_set_tuning.argtypes = [c_void_p, P(lg_tuning)]
@@ -294,8 +294,10 @@ def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_tabl
 
 
 def lg_score(pocket: Pocket, poses: DeviceLigands, interp: int = LG_TRILINEAR, grad: bool = False,
-             top_m: int = 0, stream=None):
-    """Score poses; returns dict(score [n], grad [6n + total_torsions] or None, top_idx, top_score)."""
+             top_m: int = 0, moves=None, stream=None):
+    """Score poses (optionally moved by local parameters `moves`, a device tensor of
+    6n + total_torsions floats); returns dict(score [n], grad [6n + total_torsions]
+    or None, top_idx, top_score)."""
     torch = _torch()
     dev = poses.x.device
     n = poses.n
@@ -304,8 +306,9 @@ def lg_score(pocket: Pocket, poses: DeviceLigands, interp: int = LG_TRILINEAR, g
     res["top_idx"] = torch.empty(max(top_m, 1), dtype=torch.int32, device=dev)[:top_m] if top_m else None
     res["top_score"] = torch.empty(max(top_m, 1), dtype=torch.float32, device=dev)[:top_m] if top_m else None
     L = poses.struct()
-    _check(_lib.lg_score(pocket.handle, ctypes.byref(L), int(interp), _ptr(res["score"]), _ptr(res["grad"]),
-                         int(top_m), _ptr(res["top_idx"]), _ptr(res["top_score"]), _stream_handle(stream)))
+    _check(_lib.lg_score(pocket.handle, ctypes.byref(L), int(interp), _ptr(moves), _ptr(res["score"]),
+                         _ptr(res["grad"]), int(top_m), _ptr(res["top_idx"]), _ptr(res["top_score"]),
+                         _stream_handle(stream)))
     return res
 
 

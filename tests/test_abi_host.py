@@ -59,7 +59,7 @@ def test_argument_checks_need_no_device():
     lib = lg.load_library()
     assert lib.lg_dock_batch(None, None, None, None, None) == lg.LG_ERR_INVALID_ARG
     assert "NULL" in lg.lg_last_error()
-    assert lib.lg_score(None, None, 0, None, None, 0, None, None, None) == lg.LG_ERR_INVALID_ARG
+    assert lib.lg_score(None, None, 0, None, None, None, 0, None, None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_refine(None, None, None, None, None, None, None, None) != lg.LG_OK
     assert lib.lg_set_tuning(None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_free_pocket(None) == lg.LG_OK

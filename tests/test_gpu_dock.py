@@ -216,3 +216,46 @@ def test_device_validation_errors(lgmod, tiny):
 def device_ligands_ok(lg, L):
     return lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
                              L.inv_bond_len, L.ref_point)
+
+
+def test_refine_matches_oracle(lgmod, tiny):
+    """lg_refine on docked poses: best pose and score bitwise equal to the FP32
+    oracle's refinement (same step script, same step polynomial, sums in atom
+    order)."""
+    lg = lgmod
+    import torch
+    w, pk, L = tiny["w"], tiny["pocket"], tiny["ligs"]
+    pocket = device_pocket(pk)
+    k = 2
+    out = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], T=w.angle_samples, S=w.sweeps, top_k=k, mode=lg.LG_BUCKETED,
+                   trace=False, all_scores=False)
+    # poses batch: every ligand's top-k poses, pivot = FP32 centroid of the pose
+    parts, idx = [], []
+    for i in range(L.n):
+        for q in range(k):
+            a0, a1 = L.atom_offset[i], L.atom_offset[i + 1]
+            base = k * a0 + q * (a1 - a0)
+            xyz = np.stack([out["x"][base:base + a1 - a0], out["y"][base:base + a1 - a0],
+                            out["z"][base:base + a1 - a0]], 1)
+            parts.append(xyz)
+            idx.append(i)
+    Lp = L.subset(np.array(idx))
+    xyz_all = np.concatenate(parts)
+    cen = np.stack([p.astype(np.float64).mean(0) for p in parts]).astype(np.float32)
+    dl = lg.device_ligands(Lp.atom_offset, Lp.tors_offset, xyz_all[:, 0], xyz_all[:, 1], xyz_all[:, 2],
+                           Lp.frag_mask, Lp.tors_atoms, Lp.inv_bond_len, cen.reshape(-1))
+    prm = lg.lg_refine_params(50, 1e-2, 1e-3, 1e-3, 0.1, 0.05, 0.1, oracle.CLASH2)
+    res = lg.lg_refine(pocket, dl, prm)
+    torch.cuda.synchronize()
+    rx, ry, rz, rs = (res[c].cpu().numpy() for c in ("x", "y", "z", "score"))
+    moved = 0
+    for j in range(Lp.n):
+        lig = Lp.ligand(j)
+        a0, a1 = Lp.atom_offset[j], Lp.atom_offset[j + 1]
+        s, best, acc = oracle.refine(lig, pk, parts[j].astype(np.float64), cen[j].astype(np.float64), bits=32)
+        got = np.stack([rx[a0:a1], ry[a0:a1], rz[a0:a1]], 1).astype(np.float64)
+        np.testing.assert_array_equal(got, best, err_msg=f"refined pose {j}")
+        assert rs[j] == s, (j, rs[j], s)
+        moved += not np.array_equal(best, parts[j].astype(np.float64))
+    assert moved > Lp.n // 2
+    pocket.free()
