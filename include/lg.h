@@ -138,6 +138,9 @@ typedef struct {
   float* all_scores;         /* optional */
   int16_t* trace;            /* optional */
   int32_t trace_kmax;
+  float* pivot;              /* optional [n*top_k*3]: rigid-body pivot of each kept pose
+                                (ref_point carried through placement and translations),
+                                the pivot lg_refine rotates about */
 } lg_dock_out;
 
 /* Load a docking site: copies the grid (host or device memory, per
@@ -182,17 +185,34 @@ lg_status lg_score(lg_pocket pocket, const lg_ligands* poses, int32_t interp, co
  * eta_th*g_th) clipped to norm clip_t, norm clip_w and per-bond clip_th,
  * applied as the local move of lg_score; a step that makes an intramolecular
  * clash (any pair separated by a rotatable bond, other than the bond's own
- * axis atoms, closer than sqrt(clash_dist2)) is rejected and the pose kept.
- * The best-scoring pose seen (including the input) is returned. */
+ * axis atoms, closer than sqrt(clash_dist2)) is rejected, the pose kept and
+ * the step scale of later steps halved.  The best-scoring pose seen (including
+ * the input) is written to x/y/z_out in the layout of the input coordinates,
+ * its score to score_out [n*k].  One wavefront refines one pose. */
 typedef struct {
   int32_t steps;
   float eta_t, eta_w, eta_th;
-  float clip_t, clip_w, clip_th;
+  float clip_t, clip_w, clip_th;  /* clip_w and clip_th in (0, pi/4] */
   float clash_dist2;
+  int32_t poses_per_ligand;       /* k >= 1.  k = 1: entry i of `poses` is one pose.  k > 1:
+                                     x/y/z hold k poses per ligand in the lg_dock_out layout
+                                     (pose q of ligand i at k*atom_offset[i] + q*N_i) and
+                                     ref_point holds one pivot per pose [3*(k*i + q)] */
 } lg_refine_params;
 
 lg_status lg_refine(lg_pocket pocket, const lg_ligands* poses, const lg_refine_params* params,
                     float* x_out, float* y_out, float* z_out, float* score_out, void* stream);
+
+/* Rank a library (Sec. 2 "rank the input chemical library"): score holds
+ * group_size consecutive values per ligand (device [n_groups*group_size], e.g.
+ * lg_refine's scores of a ligand's k poses); each ligand is ranked by its best
+ * value (equal values within a ligand: lower member).  top_idx / top_score
+ * (device [top_m]) receive the top_m ligands, best first, equal scores ordered
+ * by lower ligand index; top_member (optional, device [top_m]) the member that
+ * gave each ligand its score.  Uses the handle's workspace: calls on one handle
+ * must not overlap. */
+lg_status lg_rank(lg_pocket pocket, const float* score, int32_t n_groups, int32_t group_size, int32_t top_m,
+                  int32_t* top_idx, float* top_score, int32_t* top_member, void* stream);
 
 /* Tuning of the bucketed path; the autotuner sets it, the defaults work.
  * Ligands go to bucket (atom cluster, rotamer cluster): atom cluster c holds

@@ -123,7 +123,8 @@ def dock_ligand(lig, pocket, restarts, angles, T, S, trans_step, clash2, bits=32
                 want_poses=True, want_trace=True, want_scan_scores=False):
     """Dock one ligand over every row of ``restarts``.
 
-    Returns dict(final [R], poses [R,N,3], trace [R,S,6+K] int16, scan_scores [R,S,6+K])."""
+    Returns dict(final [R], poses [R,N,3], pivots [R,3], trace [R,S,6+K] int16,
+    scan_scores [R,S,6+K])."""
     lib = _load()
     keep = _Keep()
     g = _grid(pocket, keep)
@@ -132,11 +133,12 @@ def dock_ligand(lig, pocket, restarts, angles, T, S, trans_step, clash2, bits=32
     R, N, K = D.R, L.N, L.K
     final = np.zeros(R)
     poses = np.zeros((R, N, 3)) if want_poses else None
+    pivots = np.zeros((R, 3)) if want_poses else None
     trace = np.zeros((R, S, 6 + K), np.int16) if want_trace else None
     ss = np.zeros((R, S, 6 + K)) if want_scan_scores else None
     lib.oracle_dock_ligand(ctypes.c_int(bits), ctypes.byref(g), ctypes.byref(L), ctypes.byref(D),
-                           _p(final), _p(poses), _p(trace), _p(ss))
-    return dict(final=final, poses=poses, trace=trace, scan_scores=ss)
+                           _p(final), _p(poses), _p(pivots), _p(trace), _p(ss))
+    return dict(final=final, poses=poses, pivots=pivots, trace=trace, scan_scores=ss)
 
 
 def place(lig, row, center, bits=32, fp64_input=False):
@@ -282,6 +284,19 @@ def topk(scores, k):
     out = np.zeros(min(k, len(s)), np.int32)
     lib.oracle_topk(ctypes.c_int(len(s)), _p(s), ctypes.c_int(k), _p(out))
     return out
+
+
+def rank(scores, group_size, top_m):
+    """Global ranking of a library (Sec. 2: rank the chemical library by the
+    docked ligands' scores): each ligand's value is the best of its group_size
+    consecutive scores (first member on equal values); ligands by value
+    descending, equal values by lower ligand id.  Returns (ids, values, members)
+    of the first top_m."""
+    s = np.asarray(scores, np.float64).reshape(-1, group_size)
+    member = np.argmax(s, axis=1)
+    best = s[np.arange(len(s)), member]
+    order = np.lexsort((np.arange(len(best)), -best))[:top_m]
+    return order.astype(np.int32), best[order], member[order].astype(np.int32)
 
 
 def trans_step(T: int, halfwidth: float = 2.0) -> float:

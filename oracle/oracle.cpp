@@ -368,7 +368,7 @@ void from_pose(const Pose<R>& p, double* xyz, double* P) {
 
 template <class R>
 int dock_ligand(const og_grid* g, const og_ligand* l, const og_dock* d, double* final_scores,
-                double* poses, int16_t* trace, double* scan_scores) {
+                double* poses, double* pivots, int16_t* trace, double* scan_scores) {
   Ctx<R> C(g, l, d);
   int per = d->S * (6 + l->K);
   std::vector<R> ss(per);
@@ -377,6 +377,7 @@ int dock_ligand(const og_grid* g, const og_ligand* l, const og_dock* d, double* 
     R f = dock_restart(C, r, p, trace ? trace + (size_t)r * per : nullptr, scan_scores ? ss.data() : nullptr);
     final_scores[r] = (double)f;
     if (poses) from_pose(p, poses + (size_t)r * l->N * 3, (double*)nullptr);
+    if (pivots) for (int a = 0; a < 3; ++a) pivots[3 * r + a] = (double)p.P[a];
     if (scan_scores) for (int i = 0; i < per; ++i) scan_scores[(size_t)r * per + i] = (double)ss[i];
   }
   return 0;
@@ -614,12 +615,12 @@ int move_clash_free_t(const og_ligand* l, const double* xyz, double clash2) {
 }  // namespace
 
 // Dock one ligand: all restarts; final trilinear score per restart; optional
-// final poses [R][N][3], trace of selected indices [R][S][6+K] and best scan
-// score per scan [R][S][6+K].
+// final poses [R][N][3] and their pivots [R][3], trace of selected indices
+// [R][S][6+K] and best scan score per scan [R][S][6+K].
 extern "C" int oracle_dock_ligand(int real_bits, const og_grid* g, const og_ligand* l, const og_dock* d,
-                       double* final_scores, double* poses, int16_t* trace, double* scan_scores) {
-  return real_bits == 32 ? dock_ligand<float>(g, l, d, final_scores, poses, trace, scan_scores)
-                         : dock_ligand<double>(g, l, d, final_scores, poses, trace, scan_scores);
+                       double* final_scores, double* poses, double* pivots, int16_t* trace, double* scan_scores) {
+  return real_bits == 32 ? dock_ligand<float>(g, l, d, final_scores, poses, pivots, trace, scan_scores)
+                         : dock_ligand<double>(g, l, d, final_scores, poses, pivots, trace, scan_scores);
 }
 
 template <class R>

@@ -23,24 +23,19 @@ hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const Gri
 hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int tab_len, int* blocks_per_cu);
 hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr);
 hipError_t launch_topk(const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid, float* ox,
-                       float* oy, float* oz, float* all_scores, hipStream_t st);
+                       float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st);
 hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, float* score, float* grad,
                         hipStream_t st);
-hipError_t launch_rank_prep(const float* score, int n, float* keys, int32_t* vals, hipStream_t st);
+hipError_t launch_rank_prep(const float* score, int n_groups, int group, float* keys, int32_t* vals,
+                            int32_t* member, hipStream_t st);
+hipError_t launch_rank_gather(const float* keys, const int32_t* vals, const int32_t* member, int m, int32_t* top_idx,
+                              float* top_score, int32_t* top_member, hipStream_t st);
 hipError_t launch_pad(const float* src, int nx, int ny, int nz, float out, float* dst, hipStream_t st);
 hipError_t launch_brick(const float* padded, int px, int py, int pz, int nbx, int nby, int nbz, float out,
                         float* brick, hipStream_t st);
 hipError_t launch_bucketing(const int32_t* atom_offset, const int32_t* tors_offset, int n, const ClusterBounds& cb,
                             int32_t* cls, int32_t* counts, int32_t* start, int32_t* fill, int32_t* perm,
                             int32_t* cursors, hipStream_t st);
-struct RefineDev {
-  int steps;
-  float eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash2;
-  float* xo;
-  float* yo;
-  float* zo;
-  float* score;
-};
 hipError_t launch_refine(int nslot, const GridDev& G, const LigDev& P, const RefineDev& Rp, int n, hipStream_t st);
 hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, const float* moves, int n, float* score,
                               float* grad, hipStream_t st);
@@ -414,6 +409,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   const size_t o_stats = lay.take(16 * sizeof(int32_t));
   const size_t o_final = lay.take((size_t)n * R * sizeof(float));
   const size_t o_wp = lay.take((size_t)3 * R * L->total_atoms * sizeof(float));
+  const size_t o_piv = lay.take((size_t)3 * n * R * sizeof(float));
   const size_t o_cls = lay.take((size_t)n * sizeof(int32_t));
   const size_t o_perm = lay.take((size_t)n * sizeof(int32_t));
   const size_t o_cnt = lay.take((size_t)(4 * B + 1) * sizeof(int32_t));
@@ -443,6 +439,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   D.wpx = (float*)(ws + o_wp);
   D.wpy = D.wpx + (size_t)R * L->total_atoms;
   D.wpz = D.wpy + (size_t)R * L->total_atoms;
+  D.wpiv = (float*)(ws + o_piv);
   D.lazy_clash = tu.lazy_clash;
   D.trace = O->trace;
   D.trace_w = 6 + (O->trace ? O->trace_kmax : 0);
@@ -455,7 +452,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
     const int nslot = LG_MAX_ATOMS / 64;
     for (int i = 0; i < n; ++i)
       LG_HIP(lg::launch_dock_plain(nslot, spl, tu.plain_waves_per_block, p->grid, Lg, D, i, st));
-    LG_HIP(lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, st));
+    LG_HIP(lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, O->pivot, st));
     return LG_OK;
   }
 
@@ -472,7 +469,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
                                (uint64_t)R, (uint64_t)D.A, (uint64_t)D.T, (uint64_t)D.S, (uint64_t)P->top_k};
   const void* ptrs[] = {L->atom_offset, L->tors_offset, L->x, L->y, L->z, L->frag_mask, L->tors_atoms,
                         L->inv_bond_len, L->ref_point, P->restart_table, P->angle_table, O->score,
-                        O->restart_id, O->x, O->y, O->z, O->all_scores, O->trace};
+                        O->restart_id, O->x, O->y, O->z, O->all_scores, O->trace, O->pivot};
   for (const void* q : ptrs) key.push_back((uint64_t)(uintptr_t)q);
   uint32_t fb[3];
   std::memcpy(&fb[0], &D.delta, 4);
@@ -533,7 +530,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
       e = lg::launch_dock_bucket(b.slots, spl, b.waves_per_block, b.blocks, p->grid, Lg, D, Q, cs);
       if (e == hipSuccess && events) e = hipEventRecord(p->events[l + 1], cs);
     }
-    if (e == hipSuccess) e = lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, cs);
+    if (e == hipSuccess) e = lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, O->pivot, cs);
     return e;
   };
 
@@ -603,6 +600,40 @@ int32_t lg_bucket_stats(lg_pocket p, lg_bucket_stat* out, int32_t capacity) {
   return nl;
 }
 
+// Workspace of the global ranking: keys, values and members before and after
+// a stable descending radix sort (equal keys keep the lower group first).
+struct RankWs {
+  size_t k0, k1, v0, v1, mem, tmp, tmp_bytes;
+};
+
+static lg_status rank_layout(Layout& lay, int ng, hipStream_t st, RankWs* r) {
+  r->tmp_bytes = 0;
+  LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, r->tmp_bytes, (const float*)nullptr, (float*)nullptr,
+                                                        (const int32_t*)nullptr, (int32_t*)nullptr, ng, 0, 32, st));
+  r->k0 = lay.take((size_t)ng * sizeof(float));
+  r->k1 = lay.take((size_t)ng * sizeof(float));
+  r->v0 = lay.take((size_t)ng * sizeof(int32_t));
+  r->v1 = lay.take((size_t)ng * sizeof(int32_t));
+  r->mem = lay.take((size_t)ng * sizeof(int32_t));
+  r->tmp = lay.take(r->tmp_bytes + 16);
+  return LG_OK;
+}
+
+static lg_status rank_enqueue(lg_pocket p, const RankWs& r, const float* score, int ng, int group, int top_m,
+                              int32_t* top_idx, float* top_score, int32_t* top_member, hipStream_t st) {
+  char* ws = (char*)p->ws;
+  float* k0 = (float*)(ws + r.k0);
+  float* k1 = (float*)(ws + r.k1);
+  int32_t* v0 = (int32_t*)(ws + r.v0);
+  int32_t* v1 = (int32_t*)(ws + r.v1);
+  int32_t* mem = (int32_t*)(ws + r.mem);
+  size_t tmp_bytes = r.tmp_bytes;
+  LG_HIP(lg::launch_rank_prep(score, ng, group, k0, v0, top_member ? mem : nullptr, st));
+  LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(ws + r.tmp, tmp_bytes, k0, k1, v0, v1, ng, 0, 32, st));
+  LG_HIP(lg::launch_rank_gather(k1, v1, mem, top_m, top_idx, top_score, top_member, st));
+  return LG_OK;
+}
+
 lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, const float* moves, float* score, float* grad,
                    int32_t top_m, int32_t* top_idx, float* top_score, void* stream) {
   if (!p) return fail(LG_ERR_INVALID_ARG, "pocket is NULL");
@@ -617,38 +648,44 @@ lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, const float
   hipStream_t st = (hipStream_t)stream;
   LG_HIP(hipSetDevice(p->device));
   const int n = L->n;
-  size_t sort_tmp = 0;
-  if (top_m > 0)
-    LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sort_tmp, (const float*)nullptr, (float*)nullptr,
-                                                          (const int32_t*)nullptr, (int32_t*)nullptr, n, 0, 32, st));
   Layout lay;
   const size_t o_stats = lay.take(16 * sizeof(int32_t));
-  const size_t o_k0 = lay.take((size_t)n * sizeof(float));
-  const size_t o_k1 = lay.take((size_t)n * sizeof(float));
-  const size_t o_v0 = lay.take((size_t)n * sizeof(int32_t));
-  const size_t o_v1 = lay.take((size_t)n * sizeof(int32_t));
-  const size_t o_tmp = lay.take(sort_tmp + 16);
+  RankWs rw;
+  if (top_m > 0) {
+    s = rank_layout(lay, n, st, &rw);
+    if (s != LG_OK) return s;
+  }
   s = ensure_ws(p, lay.off);
   if (s != LG_OK) return s;
-  char* ws = (char*)p->ws;
   int max_atoms = 0, max_tors = 0;
-  s = check_on_device(p, L, (int32_t*)(ws + o_stats), st, &max_atoms, &max_tors);
+  s = check_on_device(p, L, (int32_t*)((char*)p->ws + o_stats), st, &max_atoms, &max_tors);
   if (s != LG_OK) return s;
   if (moves)
     LG_HIP(lg::launch_score_moves((max_atoms + 63) / 64, p->grid, lig_dev(L), moves, n, score, grad, st));
   else
     LG_HIP(lg::launch_score(p->grid, lig_dev(L), n, interp, score, grad, st));
-  if (top_m > 0) {
-    float* k0 = (float*)(ws + o_k0);
-    float* k1 = (float*)(ws + o_k1);
-    int32_t* v0 = (int32_t*)(ws + o_v0);
-    int32_t* v1 = (int32_t*)(ws + o_v1);
-    LG_HIP(lg::launch_rank_prep(score, n, k0, v0, st));
-    LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(ws + o_tmp, sort_tmp, k0, k1, v0, v1, n, 0, 32, st));
-    LG_HIP(hipMemcpyAsync(top_idx, v1, (size_t)top_m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-    LG_HIP(hipMemcpyAsync(top_score, k1, (size_t)top_m * sizeof(float), hipMemcpyDeviceToDevice, st));
-  }
+  if (top_m > 0) return rank_enqueue(p, rw, score, n, 1, top_m, top_idx, top_score, nullptr, st);
   return LG_OK;
+}
+
+lg_status lg_rank(lg_pocket p, const float* score, int32_t n_groups, int32_t group_size, int32_t top_m,
+                  int32_t* top_idx, float* top_score, int32_t* top_member, void* stream) {
+  if (!p) return fail(LG_ERR_INVALID_ARG, "pocket is NULL");
+  if (n_groups < 0 || group_size < 1) return fail(LG_ERR_INVALID_ARG, "n_groups %d < 0 or group_size %d < 1", n_groups, group_size);
+  if ((long long)n_groups * group_size > INT32_MAX) return fail(LG_ERR_LIMIT, "n_groups * group_size exceeds 2^31 - 1");
+  if (top_m < 0 || top_m > n_groups) return fail(LG_ERR_INVALID_ARG, "top_m %d outside 0..n_groups", top_m);
+  if (n_groups > 0 && !score) return fail(LG_ERR_INVALID_ARG, "score is NULL");
+  if (top_m > 0 && (!top_idx || !top_score)) return fail(LG_ERR_INVALID_ARG, "top_idx and top_score are required for top_m > 0");
+  if (top_m == 0) return LG_OK;
+  hipStream_t st = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+  Layout lay;
+  RankWs rw;
+  lg_status s = rank_layout(lay, n_groups, st, &rw);
+  if (s != LG_OK) return s;
+  s = ensure_ws(p, lay.off);
+  if (s != LG_OK) return s;
+  return rank_enqueue(p, rw, score, n_groups, group_size, top_m, top_idx, top_score, top_member, st);
 }
 
 lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp, float* x_out, float* y_out,
@@ -662,6 +699,10 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
       !std::isfinite(rp->clash_dist2) || !(rp->clip_t > 0.f) || !std::isfinite(rp->clip_t) ||
       !(rp->clip_w > 0.f) || rp->clip_w > quarter || !(rp->clip_th > 0.f) || rp->clip_th > quarter)
     return fail(LG_ERR_INVALID_ARG, "steps need finite etas, clip_t > 0 and rotation clips in (0, pi/4]");
+  if (rp->poses_per_ligand < 1) return fail(LG_ERR_INVALID_ARG, "poses_per_ligand %d < 1", rp->poses_per_ligand);
+  if ((long long)L->n * rp->poses_per_ligand > INT32_MAX / 64 ||
+      (long long)L->total_atoms * rp->poses_per_ligand > INT32_MAX)
+    return fail(LG_ERR_LIMIT, "n * poses_per_ligand or total_atoms * poses_per_ligand too large");
   if (L->n > 0 && (!x_out || !y_out || !z_out || !score_out)) return fail(LG_ERR_INVALID_ARG, "outputs are required");
   if (L->n == 0) return LG_OK;
   hipStream_t st = (hipStream_t)stream;
@@ -675,11 +716,12 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
   if (s != LG_OK) return s;
   lg::RefineDev R;
   R.steps = rp->steps;
+  R.kpl = rp->poses_per_ligand;
   R.eta_t = rp->eta_t; R.eta_w = rp->eta_w; R.eta_th = rp->eta_th;
   R.clip_t = rp->clip_t; R.clip_w = rp->clip_w; R.clip_th = rp->clip_th;
   R.clash2 = rp->clash_dist2;
   R.xo = x_out; R.yo = y_out; R.zo = z_out; R.score = score_out;
-  LG_HIP(lg::launch_refine((max_atoms + 63) / 64, p->grid, lig_dev(L), R, L->n, st));
+  LG_HIP(lg::launch_refine((max_atoms + 63) / 64, p->grid, lig_dev(L), R, L->n * rp->poses_per_ligand, st));
   return LG_OK;
 }
 

@@ -479,6 +479,8 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
       D.wpz[base + a] = p.x[2][s];
     }
   }
+  const float pv = lane == 0 ? p.piv[0] : lane == 1 ? p.piv[1] : p.piv[2];
+  if (lane < 3) D.wpiv[((size_t)lig * D.R + r) * 3 + lane] = pv;
 }
 
 // Plain method: one launch per ligand; wavefront w of the grid docks restart w.
@@ -545,7 +547,7 @@ __global__ __launch_bounds__(256) void dock_bucket_kernel(GridDev G, LigDev Lg, 
 // the copy of the selected poses.  One wavefront per ligand.
 __global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, int k, float* score,
                                                     int32_t* rid, float* ox, float* oy, float* oz,
-                                                    float* all_scores) {
+                                                    float* all_scores, float* opiv) {
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
   const int lig = blockIdx.x * nwaves + wave;
   if (lig >= n) return;
@@ -570,6 +572,7 @@ __global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, 
       score[(size_t)lig * k + qi] = fs[rs];
       rid[(size_t)lig * k + qi] = rs;
     }
+    if (opiv && lane < 3) opiv[((size_t)lig * k + qi) * 3 + lane] = D.wpiv[((size_t)lig * D.R + rs) * 3 + lane];
     const size_t src = (size_t)abase * D.R + (size_t)rs * N;
     const size_t dst = (size_t)k * abase + (size_t)qi * N;
     for (int a = lane; a < N; a += 64) {
@@ -643,11 +646,11 @@ hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr) {
 }
 
 hipError_t launch_topk(const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid, float* ox,
-                       float* oy, float* oz, float* all_scores, hipStream_t st) {
+                       float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const int wpb = 4;
   hipLaunchKernelGGL(topk_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), 0, st, Lg, D, n, k, score, rid, ox,
-                     oy, oz, all_scores);
+                     oy, oz, all_scores, pivot);
   return hipGetLastError();
 }
 

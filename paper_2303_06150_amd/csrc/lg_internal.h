@@ -59,8 +59,20 @@ struct DockDev {
   float* wpx;              // [R*total_atoms], ligand i restart r atom a at atom_offset[i]*R + r*N + a
   float* wpy;
   float* wpz;
+  float* wpiv;             // [n*R*3] pivot of each restart's final pose
   int16_t* trace;          // optional [n][R][S][trace_w]
   int trace_w;
+};
+
+// Refinement parameters and outputs.  kpl poses per ligand: pose i is member
+// i % kpl of ligand i / kpl, its coordinates at kpl*atom_offset[lig] + member*N.
+struct RefineDev {
+  int steps, kpl;
+  float eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash2;
+  float* xo;
+  float* yo;
+  float* zo;
+  float* score;
 };
 
 // Persistent work source of one bucket: items are (ligand of the bucket,

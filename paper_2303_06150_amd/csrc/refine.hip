@@ -13,15 +13,6 @@
 
 namespace lg {
 
-struct RefineDev {
-  int steps;
-  float eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash2;
-  float* xo;
-  float* yo;
-  float* zo;
-  float* score;
-};
-
 template <int NSLOT>
 struct MoveState {
   float x[3][NSLOT];
@@ -178,12 +169,14 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   int2* tors = reinterpret_cast<int2*>(pos + 64 * NSLOT);     // 32 entries (16 float4)
   float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries (8 float4)
   float* th = inv_len + 32;                                   // 32 bond gradients / steps (8 float4)
-  const int i = blockIdx.x * nwaves + wave;
+  const int i = blockIdx.x * nwaves + wave;   // pose: member i % kpl of ligand i / kpl
   if (i >= n) return;
-  const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[i]);
-  const int N = __builtin_amdgcn_readfirstlane(P.atom_offset[i + 1]) - abase;
-  const int toff = __builtin_amdgcn_readfirstlane(P.tors_offset[i]);
-  const int K = __builtin_amdgcn_readfirstlane(P.tors_offset[i + 1]) - toff;
+  const int lig = i / Rp.kpl, member = i - lig * Rp.kpl;
+  const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[lig]);
+  const int N = __builtin_amdgcn_readfirstlane(P.atom_offset[lig + 1]) - abase;
+  const int toff = __builtin_amdgcn_readfirstlane(P.tors_offset[lig]);
+  const int K = __builtin_amdgcn_readfirstlane(P.tors_offset[lig + 1]) - toff;
+  const size_t cbase = (size_t)Rp.kpl * abase + (size_t)member * N;   // coordinates of the pose
   if (lane < K) {
     tors[lane] = make_int2(P.tors_atoms[2 * (toff + lane)], P.tors_atoms[2 * (toff + lane) + 1]);
     inv_len[lane] = P.inv_len[toff + lane];
@@ -194,9 +187,9 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   for (int s = 0; s < NSLOT; ++s) {
     const int a = s * 64 + lane;
     const bool in = a < N;
-    cur.x[0][s] = in ? P.x[abase + a] : 0.f;
-    cur.x[1][s] = in ? P.y[abase + a] : 0.f;
-    cur.x[2][s] = in ? P.z[abase + a] : 0.f;
+    cur.x[0][s] = in ? P.x[cbase + a] : 0.f;
+    cur.x[1][s] = in ? P.y[cbase + a] : 0.f;
+    cur.x[2][s] = in ? P.z[cbase + a] : 0.f;
     mk[s] = in ? P.mask[abase + a] : 0u;
   }
 #pragma unroll
@@ -256,9 +249,9 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   for (int s = 0; s < NSLOT; ++s) {
     const int a = s * 64 + lane;
     if (a < N) {
-      Rp.xo[abase + a] = best.x[0][s];
-      Rp.yo[abase + a] = best.x[1][s];
-      Rp.zo[abase + a] = best.x[2][s];
+      Rp.xo[cbase + a] = best.x[0][s];
+      Rp.yo[cbase + a] = best.x[1][s];
+      Rp.zo[cbase + a] = best.x[2][s];
     }
   }
   if (lane == 0) Rp.score[i] = best_s;

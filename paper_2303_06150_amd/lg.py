@@ -25,7 +25,7 @@ LG_NEAREST, LG_TRILINEAR = 0, 1
 LG_PLAIN, LG_BUCKETED = 0, 1
 LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
 
-EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_set_tuning",
+EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_rank", "lg_set_tuning",
            "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
            "lg_last_error", "lg_version")
 
@@ -61,12 +61,14 @@ class lg_dock_params(ctypes.Structure):
 
 class lg_dock_out(ctypes.Structure):
     _fields_ = [("score", c_void_p), ("restart_id", c_void_p), ("x", c_void_p), ("y", c_void_p),
-                ("z", c_void_p), ("all_scores", c_void_p), ("trace", c_void_p), ("trace_kmax", c_int32)]
+                ("z", c_void_p), ("all_scores", c_void_p), ("trace", c_void_p), ("trace_kmax", c_int32),
+                ("pivot", c_void_p)]
 
 
 class lg_refine_params(ctypes.Structure):
     _fields_ = [("steps", c_int32), ("eta_t", c_float), ("eta_w", c_float), ("eta_th", c_float),
-                ("clip_t", c_float), ("clip_w", c_float), ("clip_th", c_float), ("clash_dist2", c_float)]
+                ("clip_t", c_float), ("clip_w", c_float), ("clip_th", c_float), ("clash_dist2", c_float),
+                ("poses_per_ligand", c_int32)]
 
 
 class lg_tuning(ctypes.Structure):
@@ -103,6 +105,7 @@ def load_library(path: str = LIB_PATH):
                              c_void_p, c_void_p]
     lib.lg_refine.argtypes = [c_void_p, P(lg_ligands), P(lg_refine_params), c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]
+    lib.lg_rank.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.lg_set_tuning.argtypes = [c_void_p, P(lg_tuning)]
     lib.lg_get_tuning.argtypes = [c_void_p, P(lg_tuning)]
     lib.lg_bucket_stats.argtypes = [c_void_p, P(lg_bucket_stat), c_int32]
@@ -112,7 +115,8 @@ def load_library(path: str = LIB_PATH):
     lib.lg_atom_clusters.argtypes = [c_int32, c_int32, c_int32, P(c_int32)]
     lib.lg_rotamer_clusters.argtypes = [c_int32, c_int32, P(c_int32)]
     lib.lg_last_error.restype = ctypes.c_char_p
-    for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_set_tuning",
+    for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_rank",
+                 "lg_set_tuning",
                  "lg_get_tuning"):
         getattr(lib, name).restype = c_int32
     _lib = lib
@@ -268,7 +272,8 @@ def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_tabl
                   trans_samples: int, trans_step: float, clash_dist2: float, mode: int = LG_BUCKETED,
                   out: dict | None = None, want_all_scores=False, trace_kmax: int | None = None, stream=None):
     """Dock a batch.  Returns a dict of device tensors: score [n,k], restart_id [n,k],
-    x/y/z [k*total_atoms], and all_scores [n,R] / trace [n,R,S,6+kmax] when asked."""
+    x/y/z [k*total_atoms], pivot [n,k,3], and all_scores [n,R] / trace [n,R,S,6+kmax]
+    when asked."""
     torch = _torch()
     R, A = int(restart_table.shape[0]), int(angle_table.shape[0])
     n, TA, dev = ligs.n, ligs.total_atoms, ligs.x.device
@@ -277,7 +282,8 @@ def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_tabl
                    restart_id=torch.empty((n, top_k), dtype=torch.int32, device=dev),
                    x=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
                    y=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
-                   z=torch.empty(top_k * TA, dtype=torch.float32, device=dev))
+                   z=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
+                   pivot=torch.empty((n, top_k, 3), dtype=torch.float32, device=dev))
         if want_all_scores:
             out["all_scores"] = torch.empty((n, R), dtype=torch.float32, device=dev)
         if trace_kmax is not None:
@@ -286,7 +292,7 @@ def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_tabl
                             float(clash_dist2), _ptr(restart_table), _ptr(angle_table))
     o = lg_dock_out(_ptr(out["score"]), _ptr(out["restart_id"]), _ptr(out["x"]), _ptr(out["y"]), _ptr(out["z"]),
                     _ptr(out.get("all_scores")), _ptr(out.get("trace")),
-                    int(trace_kmax) if out.get("trace") is not None else 0)
+                    int(trace_kmax) if out.get("trace") is not None else 0, _ptr(out.get("pivot")))
     L = ligs.struct()
     _check(_lib.lg_dock_batch(pocket.handle, ctypes.byref(L), ctypes.byref(params), ctypes.byref(o),
                               _stream_handle(stream)))
@@ -313,13 +319,44 @@ def lg_score(pocket: Pocket, poses: DeviceLigands, interp: int = LG_TRILINEAR, g
 
 
 def lg_refine(pocket: Pocket, poses: DeviceLigands, params: lg_refine_params, stream=None):
+    """Refine poses; with params.poses_per_ligand = k > 1 the coordinates hold k poses
+    per ligand (lg_dock_out layout) and ref_point one pivot per pose.  Returns
+    dict(x, y, z [k*total_atoms], score [n*k])."""
     torch = _torch()
     dev = poses.x.device
-    TA = poses.total_atoms
+    k = max(int(params.poses_per_ligand), 1)
+    TA = k * poses.total_atoms
     out = dict(x=torch.empty(TA, dtype=torch.float32, device=dev), y=torch.empty(TA, dtype=torch.float32, device=dev),
                z=torch.empty(TA, dtype=torch.float32, device=dev),
-               score=torch.empty(max(poses.n, 1), dtype=torch.float32, device=dev)[:poses.n])
+               score=torch.empty(max(poses.n * k, 1), dtype=torch.float32, device=dev)[:poses.n * k])
     L = poses.struct()
     _check(_lib.lg_refine(pocket.handle, ctypes.byref(L), ctypes.byref(params), _ptr(out["x"]), _ptr(out["y"]),
                           _ptr(out["z"]), _ptr(out["score"]), _stream_handle(stream)))
     return out
+
+
+def refine_params(steps=50, eta_t=1e-2, eta_w=1e-3, eta_th=1e-3, clip_t=0.1, clip_w=0.05, clip_th=0.1,
+                  clash_dist2=4.84, poses_per_ligand=1) -> lg_refine_params:
+    return lg_refine_params(int(steps), eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash_dist2,
+                            int(poses_per_ligand))
+
+
+def lg_rank(pocket: Pocket, score, group_size: int, top_m: int, stream=None):
+    """Rank ligands by the best of their group_size consecutive scores.  Returns
+    dict(top_idx [top_m] ligand ids, top_score [top_m], top_member [top_m])."""
+    torch = _torch()
+    dev = score.device
+    ng = int(score.numel()) // int(group_size)
+    res = {k: torch.empty(max(top_m, 1), dtype=dt, device=dev)[:top_m]
+           for k, dt in (("top_idx", torch.int32), ("top_score", torch.float32), ("top_member", torch.int32))}
+    _check(_lib.lg_rank(pocket.handle, _ptr(score), ng, int(group_size), int(top_m), _ptr(res["top_idx"]),
+                        _ptr(res["top_score"]), _ptr(res["top_member"]), _stream_handle(stream)))
+    return res
+
+
+def docked_poses(ligs: DeviceLigands, out: dict) -> DeviceLigands:
+    """The kept poses of an lg_dock_batch result as refinement input: the ligands'
+    topology with the output coordinates and pivots (k poses per ligand)."""
+    return DeviceLigands(ligs.n, ligs.atom_offset, ligs.tors_offset, out["x"], out["y"], out["z"], ligs.frag_mask,
+                         ligs.tors_atoms, ligs.inv_bond_len, out["pivot"].reshape(-1), ligs.atom_offset_host,
+                         ligs.tors_offset_host)

@@ -78,3 +78,6 @@ def compare_ligand(out, L, i, ref, rows, top_k, R, label=""):
         for q in range(top_k):
             np.testing.assert_array_equal(pose_of(out, L, i, q, top_k).astype(np.float64), ref["poses"][idx[q]],
                                           err_msg=f"{label} ligand {i} rank {q} pose")
+            if "pivot" in out:
+                np.testing.assert_array_equal(out["pivot"][i, q].astype(np.float64), ref["pivots"][idx[q]],
+                                              err_msg=f"{label} ligand {i} rank {q} pivot")

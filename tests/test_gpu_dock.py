@@ -9,7 +9,7 @@ import pytest
 
 import gen
 import oracle
-from gpu_common import compare_ligand, dock_gpu, dock_oracle, device_pocket, say
+from gpu_common import compare_ligand, dock_gpu, dock_oracle, device_pocket, pose_of, say
 
 pytestmark = pytest.mark.gpu
 
@@ -244,7 +244,7 @@ def test_refine_matches_oracle(lgmod, tiny):
     cen = np.stack([p.astype(np.float64).mean(0) for p in parts]).astype(np.float32)
     dl = lg.device_ligands(Lp.atom_offset, Lp.tors_offset, xyz_all[:, 0], xyz_all[:, 1], xyz_all[:, 2],
                            Lp.frag_mask, Lp.tors_atoms, Lp.inv_bond_len, cen.reshape(-1))
-    prm = lg.lg_refine_params(50, 1e-2, 1e-3, 1e-3, 0.1, 0.05, 0.1, oracle.CLASH2)
+    prm = lg.refine_params(clash_dist2=oracle.CLASH2)
     res = lg.lg_refine(pocket, dl, prm)
     torch.cuda.synchronize()
     rx, ry, rz, rs = (res[c].cpu().numpy() for c in ("x", "y", "z", "score"))
@@ -259,3 +259,49 @@ def test_refine_matches_oracle(lgmod, tiny):
         moved += not np.array_equal(best, parts[j].astype(np.float64))
     assert moved > Lp.n // 2
     pocket.free()
+
+
+def test_dock_refine_rank_pipeline(lgmod, tiny):
+    """Dock (top-k with pivots) -> refine every kept pose in place (k poses per
+    ligand, pivots from docking) -> rank ligands by their best refined pose, all
+    against the oracle on the same inputs."""
+    lg = lgmod
+    import torch
+    w, pk, L = tiny["w"], tiny["pocket"], tiny["ligs"]
+    pocket = device_pocket(pk)
+    k = 3
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                           L.inv_bond_len, L.ref_point)
+    rt = torch.from_numpy(tiny["r32"]).cuda()
+    at = torch.from_numpy(tiny["a32"]).cuda()
+    out = lg.lg_dock_batch(pocket, dl, rt, at, sweeps=w.sweeps, top_k=k, trans_samples=w.angle_samples,
+                           trans_step=oracle.trans_step(w.angle_samples), clash_dist2=oracle.CLASH2)
+    res = lg.lg_refine(pocket, lg.docked_poses(dl, out), lg.refine_params(clash_dist2=oracle.CLASH2, poses_per_ligand=k))
+    top_m = 20
+    rk = lg.lg_rank(pocket, res["score"], k, top_m)
+    torch.cuda.synchronize()
+    h = {key: v.cpu().numpy() for key, v in out.items()}
+    r = {key: v.cpu().numpy() for key, v in res.items()}
+    ref_scores = np.zeros((L.n, k))
+    for i in range(L.n):
+        ref = dock_oracle(pk, L, i, tiny["r32"], tiny["a32"], T=w.angle_samples, S=w.sweeps)
+        idx = oracle.topk(ref["final"], k)
+        lig = L.ligand(i)
+        for q in range(k):
+            P = ref["pivots"][idx[q]]
+            np.testing.assert_array_equal(h["pivot"][i, q].astype(np.float64), P, err_msg=f"pivot {i},{q}")
+            s, best, _ = oracle.refine(lig, pk, ref["poses"][idx[q]], P, bits=32)
+            got = pose_of(r, L, i, q, k).astype(np.float64)
+            np.testing.assert_array_equal(got, best, err_msg=f"refined pose of ligand {i} rank {q}")
+            assert r["score"][i * k + q] == s
+            ref_scores[i, q] = s
+    ids, vals, members = oracle.rank(ref_scores.reshape(-1), k, top_m)
+    np.testing.assert_array_equal(rk["top_idx"].cpu().numpy(), ids)
+    np.testing.assert_array_equal(rk["top_score"].cpu().numpy().astype(np.float64), vals)
+    np.testing.assert_array_equal(rk["top_member"].cpu().numpy(), members)
+    # ranking a single score per ligand through lg_score's top_m agrees with lg_rank
+    one = lg.lg_rank(pocket, res["score"], 1, 10)
+    ids1, vals1, _ = oracle.rank(ref_scores.reshape(-1), 1, 10)
+    np.testing.assert_array_equal(one["top_idx"].cpu().numpy(), ids1)
+    pocket.free()
+

@@ -314,14 +314,19 @@ def test_rigid_and_bond_invariants_fp64(tiny):
         mask = lig["frag_mask"]
         same = mask[:, None] == mask[None, :]
         bonds = [(c, p) for c, p in enumerate(lig["parent"]) if p >= 0]
+        root = mask == 0
         for r in range(3):
-            start, _ = oracle.place(lig, tiny["r64"][r], pk.center.astype(np.float64), bits=64, fp64_input=True)
+            start, P0 = oracle.place(lig, tiny["r64"][r], pk.center.astype(np.float64), bits=64, fp64_input=True)
             d0 = np.linalg.norm(start[:, None] - start[None], axis=-1)
             d1 = np.linalg.norm(out["poses"][r][:, None] - out["poses"][r][None], axis=-1)
             np.testing.assert_allclose(d1[same], d0[same], atol=1e-9)
             for c, p in bonds:
                 assert abs(d1[c, p] - 1.5) < 1e-9
             assert not np.allclose(d1, d0)   # the torsions did move something
+            # the pivot rides with the rigid root piece: rotations turn about it,
+            # translations carry it along
+            np.testing.assert_allclose(np.linalg.norm(out["poses"][r][root] - out["pivots"][r], axis=1),
+                                       np.linalg.norm(start[root] - P0, axis=1), atol=1e-9)
 
 
 def test_fp32_invariants_and_axis_bond_exact(tiny):
@@ -393,6 +398,23 @@ def test_topk_is_a_sort():
         idx = oracle.topk(s, k)
         expect = np.lexsort((np.arange(len(s)), -s))[:k]
         np.testing.assert_array_equal(idx, expect)
+
+
+def test_rank_is_a_grouped_selection():
+    rng = np.random.default_rng(6)
+    for g in (1, 3, 8):
+        s = np.round(rng.normal(size=(97, g)) * 3) / 4       # ties within and across ligands
+        ids, vals, members = oracle.rank(s.reshape(-1), g, 40)
+        left = list(range(97))
+        for q in range(40):
+            # brute force: scan every remaining ligand and member, strict > keeps the first
+            bi, bm, bv = -1, -1, -np.inf
+            for i in left:
+                for m in range(g):
+                    if s[i, m] > bv:
+                        bi, bm, bv = i, m, s[i, m]
+            assert (ids[q], members[q], vals[q]) == (bi, bm, bv)
+            left.remove(bi)
 
 
 # ---------------------------------------------------------------- adjoint
