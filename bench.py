@@ -145,6 +145,12 @@ def main():
     ap.add_argument("--ligands", type=int, default=None, help="use the first n ligands of the workload")
     ap.add_argument("--plain-ligands", type=int, default=2000)
     ap.add_argument("--ablation-ligands", type=int, default=20000)
+    ap.add_argument("--autotune-ligands", type=int, default=4000,
+                    help="tune the bucketed path on this many ligands before timing (0: default tuning)")
+    ap.add_argument("--refine-ligands", type=int, default=20000,
+                    help="side run: refine the top --refine-poses poses of this many ligands (0: skip)")
+    ap.add_argument("--refine-poses", type=int, default=64)
+    ap.add_argument("--refine-steps", type=int, default=50)
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side-runs", action="store_true", help="skip the plain and ablation runs")
@@ -189,6 +195,23 @@ def main():
 
     def dock(ligs, mode, out=None):
         return lg.lg_dock_batch(pocket, ligs, rt, at, mode=mode, out=out, **kw)
+
+    # ---- autotuning on a prefix of the library (reported, not timed)
+    tune = None
+    if args.autotune_ligands > 0:
+        nt = min(args.autotune_ligands, n)
+        Lt = L.subset(np.arange(nt))
+        dlt = lg.device_ligands(Lt.atom_offset, Lt.tors_offset, Lt.x, Lt.y, Lt.z, Lt.frag_mask, Lt.tors_atoms,
+                                Lt.inv_bond_len, Lt.ref_point)
+        t0 = time.perf_counter()
+        tt, tms = lg.lg_autotune(pocket, dlt, rt, at, **kw)
+        tune = dict(ligands=nt, seconds=round(time.perf_counter() - t0, 2), sample_ms=round(tms, 3),
+                    restart_chunk=tt.restart_chunk, grid_scale=tt.grid_scale,
+                    waves_per_block=list(tt.waves_per_block), lazy_clash=tt.lazy_clash,
+                    atom_bounds=list(tt.atom_bounds[:tt.n_atom_clusters]),
+                    rot_bounds=list(tt.rot_bounds[:tt.n_rot_clusters]))
+        log(f"autotune on {nt} ligands: {tune}")
+        del dlt
 
     # ---- bucketed persistent path: the timed steps
     out = None
@@ -292,6 +315,36 @@ def main():
                                            bucketed_same_ligands=round(nab / buck_ab_s, 2))
         log(f"one-bucket ablation: {nab / abl_s:.1f} ligands/s vs bucketed {nab / buck_ab_s:.1f} on {nab}")
 
+        # refinement of the kept poses (k per ligand, about their docking pivots) and the
+        # global ranking of the ligands by their best refined pose
+        nrf = min(args.refine_ligands, n)
+        if nrf > 0:
+            kp = args.refine_poses
+            Lr = L.subset(np.arange(nrf))
+            dlr = lg.device_ligands(Lr.atom_offset, Lr.tors_offset, Lr.x, Lr.y, Lr.z, Lr.frag_mask, Lr.tors_atoms,
+                                    Lr.inv_bond_len, Lr.ref_point)
+            od = lg.lg_dock_batch(pocket, dlr, rt, at, mode=lg.LG_BUCKETED, **dict(kw, top_k=kp))
+            poses = lg.docked_poses(dlr, od)
+            prm = lg.refine_params(steps=args.refine_steps, clash_dist2=clash2, poses_per_ligand=kp)
+            lg.lg_refine(pocket, poses, prm)
+            torch.cuda.synchronize()
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            rf = lg.lg_refine(pocket, poses, prm)
+            e1.record()
+            rk = lg.lg_rank(pocket, rf["score"], kp, min(1000, nrf))
+            e2.record()
+            torch.cuda.synchronize()
+            rms = e0.elapsed_time(e1)
+            gain = (rf["score"].reshape(nrf, kp) - od["score"]).double()
+            side["refine"] = dict(ligands=nrf, poses=nrf * kp, steps=args.refine_steps, ms=round(rms, 3),
+                                  value=round(nrf * kp / (rms * 1e-3), 1), unit="poses/s",
+                                  mean_score_gain=round(float(gain.mean()), 4),
+                                  rank_top_m=min(1000, nrf), rank_ms=round(e1.elapsed_time(e2), 3))
+            log(f"refine: {nrf * kp} poses x {args.refine_steps} steps in {rms:.1f} ms "
+                f"({nrf * kp / (rms * 1e-3):.0f} poses/s); ranking {e1.elapsed_time(e2):.3f} ms")
+            del od, poses, rf, rk
+
     if args.copy_calibration:
         # an elementwise kernel that reads 1 GiB and writes 1 GiB (a device-to-device
         # copy_ would go to the DMA engines and not show up as a kernel)
@@ -325,7 +378,7 @@ def main():
                              f"A=T={w.angle_samples}, S={w.sweeps}, top-{w.top_k}",
                     ligands=n, restarts=w.restarts, angle_samples=w.angle_samples, sweeps=w.sweeps,
                     top_k=w.top_k, mode="bucketed persistent, one HIP graph"),
-        roofline=roofline, cpu_baseline=cpu,
+        roofline=roofline, cpu_baseline=cpu, autotune=tune,
         algorithmic_top_s_whole_step=round(total_ops / (ms_per_step * 1e-3) / 1e12, 3),
         speedup_vs_plain=round(value / side["plain"]["value"], 2) if "plain" in side else None,
         buckets=buckets, **side)

@@ -242,6 +242,21 @@ typedef struct {
 lg_status lg_set_tuning(lg_pocket pocket, const lg_tuning* tuning);
 lg_status lg_get_tuning(lg_pocket pocket, lg_tuning* tuning);
 
+/* Autotuner of the bucketed path (the input-aware choices of Sec. 3 -- size
+ * buckets and kernel shapes -- searched by measurement on the device).  Docks
+ * the sample `ligands` with `params` (mode ignored: bucketed) repeatedly under
+ * candidate tunings and keeps, by coordinate descent over `passes` rounds, any
+ * candidate at least 1 % faster: size buckets (one per kernel instance, with
+ * or without rotamer clusters, or a single bucket), wavefronts per block of
+ * each instance in use, restart chunk, persistent grid scale and the clash
+ * test variant.  Times are the bucket launches of one call (events between
+ * launches), best of two.  On success the handle keeps the best tuning (its
+ * use_graph setting unchanged), *out receives it and *best_ms (optional) its
+ * time; on failure the handle's tuning is restored.  Results never depend on
+ * the tuning.  Synchronises `stream`; allocates its trial outputs. */
+lg_status lg_autotune(lg_pocket pocket, const lg_ligands* ligands, const lg_dock_params* params, int32_t passes,
+                      lg_tuning* out, float* best_ms, void* stream);
+
 /* Per-bucket report of the last LG_BUCKETED call on a handle -- the MI355X
  * analog of the paper's Table 1 (registers and resident blocks per size class)
  * plus the launch duration, measured with events recorded in the graph around

@@ -476,6 +476,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   std::memcpy(&fb[1], &D.clash2, 4);
   fb[2] = (uint32_t)O->trace_kmax;
   for (uint32_t v : fb) key.push_back(v);
+  key.push_back((uint64_t)max_atoms);   // sizes the kernel instances of the plan
 
   lg::ClusterBounds cb;
   std::memset(&cb, 0, sizeof cb);
@@ -489,7 +490,9 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   auto plan = [&](std::vector<lg_bucket_stat>& launches) -> lg_status {
     // Eq. 1: resident blocks per CU of each instance give the persistent grid
     for (int ca = cb.na - 1; ca >= 0; --ca) {
-      const int nslot = (cb.atom[ca] + 63) / 64;
+      // the instance holds the cluster's largest possible ligand: its bound, or the
+      // batch's largest ligand if that is smaller (the last bound is LG_MAX_ATOMS)
+      const int nslot = std::max(1, (std::min(cb.atom[ca], max_atoms) + 63) / 64);
       const int wpb = tu.waves_per_block[nslot - 1];
       int bpc = 0;
       LG_HIP(lg::occupancy_dock_bucket(nslot, spl, wpb, p->grid.tab_len, &bpc));
@@ -598,6 +601,133 @@ int32_t lg_bucket_stats(lg_pocket p, lg_bucket_stat* out, int32_t capacity) {
     out[l].ms = ms;
   }
   return nl;
+}
+
+lg_status lg_autotune(lg_pocket p, const lg_ligands* L, const lg_dock_params* P, int32_t passes, lg_tuning* out,
+                      float* best_ms, void* stream) {
+  if (!p || !P || !out) return fail(LG_ERR_INVALID_ARG, "pocket, params and out must not be NULL");
+  lg_status s = check_ligands(L, true);
+  if (s != LG_OK) return s;
+  if (L->n < 1) return fail(LG_ERR_INVALID_ARG, "the tuning sample is empty");
+  if (passes < 1 || passes > 8) return fail(LG_ERR_INVALID_ARG, "passes %d outside 1..8", passes);
+  if (P->top_k < 1 || P->top_k > P->restarts) return fail(LG_ERR_INVALID_ARG, "top_k %d outside 1..R", P->top_k);
+  hipStream_t st = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+
+  // largest ligand and bond count of the sample
+  Layout lay;
+  const size_t o_stats = lay.take(16 * sizeof(int32_t));
+  s = ensure_ws(p, lay.off);
+  if (s != LG_OK) return s;
+  int max_atoms = 0, max_tors = 0;
+  s = check_on_device(p, L, (int32_t*)((char*)p->ws + o_stats), st, &max_atoms, &max_tors);
+  if (s != LG_OK) return s;
+
+  // outputs of the trial calls
+  const size_t nk = (size_t)L->n * P->top_k, ak = (size_t)L->total_atoms * P->top_k;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, (nk * 5 + 3 * ak) * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LG_ERR_OUT_OF_MEMORY, "autotuner outputs could not be allocated");
+  }
+  float* f = (float*)buf;
+  lg_dock_out O;
+  std::memset(&O, 0, sizeof O);
+  O.score = f;
+  O.restart_id = (int32_t*)(f + nk);
+  O.pivot = f + 2 * nk;
+  O.x = f + 5 * nk;
+  O.y = O.x + ak;
+  O.z = O.y + ak;
+  lg_dock_params tp = *P;
+  tp.mode = LG_BUCKETED;
+  const lg_tuning saved = p->tuning;
+
+  // time of the bucket launches of one call (events recorded between them), best of two
+  auto trial = [&](lg_tuning t, float* ms) -> lg_status {
+    t.use_graph = 0;
+    lg_status r = lg_set_tuning(p, &t);
+    if (r != LG_OK) return r;
+    float best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      r = lg_dock_batch(p, L, &tp, &O, stream);
+      if (r != LG_OK) return r;
+      LG_HIP(hipStreamSynchronize(st));
+      float m = 0.f;
+      LG_HIP(hipEventElapsedTime(&m, p->events[0], p->events[p->launches.size()]));
+      best = std::min(best, m);
+    }
+    *ms = best;
+    return LG_OK;
+  };
+
+  lg_tuning cur = saved;
+  float cur_ms = 0.f;
+  s = trial(cur, &cur_ms);
+  // a candidate replaces the current choice only if it is at least 1 % faster
+  auto consider = [&](const lg_tuning& t) -> lg_status {
+    float ms = 0.f;
+    lg_status r = trial(t, &ms);
+    if (r == LG_OK && ms < 0.99f * cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+    return r;
+  };
+  for (int pass = 0; pass < passes && s == LG_OK; ++pass) {
+    // size buckets: one cluster per kernel instance (atom slots), with or without
+    // rotamer clusters, or one cluster for everything
+    {
+      lg_tuning t = cur;
+      t.n_atom_clusters = lg_atom_clusters(4, 64, std::max(max_atoms, 1), t.atom_bounds);
+      t.n_rot_clusters = 1;
+      t.rot_bounds[0] = LG_MAX_TORSIONS;
+      if (s == LG_OK) s = consider(t);
+      t.n_rot_clusters = lg_rotamer_clusters(4, std::max(max_tors, 1), t.rot_bounds);
+      if (s == LG_OK && t.n_rot_clusters > 1) s = consider(t);
+      t.n_atom_clusters = 1;
+      t.atom_bounds[0] = LG_MAX_ATOMS;
+      t.n_rot_clusters = 1;
+      t.rot_bounds[0] = LG_MAX_TORSIONS;
+      if (s == LG_OK) s = consider(t);
+    }
+    // wavefronts per block of each kernel instance in use
+    for (int slots = 1; slots <= (max_atoms + 63) / 64 && s == LG_OK; ++slots)
+      for (int w : {1, 2, 4}) {
+        if (w == cur.waves_per_block[slots - 1] || s != LG_OK) continue;
+        lg_tuning t = cur;
+        t.waves_per_block[slots - 1] = w;
+        s = consider(t);
+      }
+    for (int c : {2, 4, 8, 16, 32}) {
+      if (c == cur.restart_chunk || c > P->restarts || s != LG_OK) continue;
+      lg_tuning t = cur;
+      t.restart_chunk = c;
+      s = consider(t);
+    }
+    for (int g : {1, 2, 4}) {
+      if (g == cur.grid_scale || s != LG_OK) continue;
+      lg_tuning t = cur;
+      t.grid_scale = g;
+      s = consider(t);
+    }
+    if (s == LG_OK) {
+      lg_tuning t = cur;
+      t.lazy_clash = 1 - cur.lazy_clash;
+      s = consider(t);
+    }
+  }
+  (void)hipFree(buf);
+  if (s != LG_OK) {
+    p->tuning = saved;
+    return s;
+  }
+  cur.use_graph = saved.use_graph;
+  lg_status r = lg_set_tuning(p, &cur);
+  if (r != LG_OK) return r;
+  *out = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return LG_OK;
 }
 
 // Workspace of the global ranking: keys, values and members before and after

@@ -539,6 +539,12 @@ __global__ __launch_bounds__(256) void dock_bucket_kernel(GridDev G, LigDev Lg, 
       cur_lig = lig;
     }
     const int r0 = ch * Q.chunk, r1 = min(D.R, r0 + Q.chunk);
+    if (L.N > 64 * NSLOT) {
+      // cannot happen with the host's plan (instances sized for the largest
+      // ligand); marks the restarts instead of touching memory out of range
+      for (int r = r0 + lane; r < r1; r += 64) D.final_scores[(size_t)lig * D.R + r] = __builtin_nanf("");
+      continue;
+    }
     for (int r = r0; r < r1; ++r) dock_restart(G, Lg, D, sm, L, lig, r, scr, cand, tab);
   }
 }

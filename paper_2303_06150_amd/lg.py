@@ -25,8 +25,8 @@ LG_NEAREST, LG_TRILINEAR = 0, 1
 LG_PLAIN, LG_BUCKETED = 0, 1
 LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
 
-EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_rank", "lg_set_tuning",
-           "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
+EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_rank", "lg_autotune",
+           "lg_set_tuning", "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
            "lg_last_error", "lg_version")
 
 
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     lib.lg_refine.argtypes = [c_void_p, P(lg_ligands), P(lg_refine_params), c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]
     lib.lg_rank.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.lg_autotune.argtypes = [c_void_p, P(lg_ligands), P(lg_dock_params), c_int32, P(lg_tuning),
+                                P(c_float), c_void_p]
     lib.lg_set_tuning.argtypes = [c_void_p, P(lg_tuning)]
     lib.lg_get_tuning.argtypes = [c_void_p, P(lg_tuning)]
     lib.lg_bucket_stats.argtypes = [c_void_p, P(lg_bucket_stat), c_int32]
@@ -116,8 +118,7 @@ def load_library(path: str = LIB_PATH):
     lib.lg_rotamer_clusters.argtypes = [c_int32, c_int32, P(c_int32)]
     lib.lg_last_error.restype = ctypes.c_char_p
     for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_rank",
-                 "lg_set_tuning",
-                 "lg_get_tuning"):
+                 "lg_autotune", "lg_set_tuning", "lg_get_tuning"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -297,6 +298,21 @@ def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_tabl
     _check(_lib.lg_dock_batch(pocket.handle, ctypes.byref(L), ctypes.byref(params), ctypes.byref(o),
                               _stream_handle(stream)))
     return out
+
+
+def lg_autotune(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_table, *, sweeps: int, top_k: int,
+                trans_samples: int, trans_step: float, clash_dist2: float, passes: int = 1, stream=None):
+    """Search the bucketed path's tuning on a sample batch; the handle keeps the
+    best.  Returns (lg_tuning, best_ms)."""
+    R, A = int(restart_table.shape[0]), int(angle_table.shape[0])
+    params = lg_dock_params(R, A, int(trans_samples), int(sweeps), int(top_k), LG_BUCKETED, float(trans_step),
+                            float(clash_dist2), _ptr(restart_table), _ptr(angle_table))
+    t = lg_tuning()
+    ms = c_float(0.0)
+    L = ligs.struct()
+    _check(_lib.lg_autotune(pocket.handle, ctypes.byref(L), ctypes.byref(params), int(passes), ctypes.byref(t),
+                            ctypes.byref(ms), _stream_handle(stream)))
+    return t, float(ms.value)
 
 
 def lg_score(pocket: Pocket, poses: DeviceLigands, interp: int = LG_TRILINEAR, grad: bool = False,

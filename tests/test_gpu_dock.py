@@ -124,6 +124,8 @@ def test_determinism_and_batch_order(lgmod, tiny):
         np.testing.assert_array_equal(a[key], d[key])
     assert sum(b["ligands"] for b in stats) == L.n
     assert all(b["ms"] >= 0 for b in stats)
+    # every instance is sized for the batch's largest ligand (at most 40 atoms here)
+    assert all(b["slots"] == 1 for b in stats)
     # other tunings (one bucket, rotamer clusters, chunking): same bits
     o = lg.lg_tuning.from_buffer_copy(t)
     o.n_atom_clusters, o.n_rot_clusters, o.restart_chunk = 2, 3, 3
@@ -305,3 +307,34 @@ def test_dock_refine_rank_pipeline(lgmod, tiny):
     np.testing.assert_array_equal(one["top_idx"].cpu().numpy(), ids1)
     pocket.free()
 
+
+
+def test_autotune_keeps_results(lgmod):
+    """The autotuner returns a valid tuning that the handle keeps, and docking
+    under it gives the same bits as under the default tuning."""
+    lg = lgmod
+    import torch
+    w = gen.WORKLOADS["mixed"]
+    L = gen.workload_ligands(w, np.arange(600, dtype=np.int64))
+    pk = gen.workload_pocket(w)
+    r32, _ = gen.restarts(64, w.seed)
+    a32, _ = gen.angles(w.angle_samples)
+    pocket = device_pocket(pk)
+    kw = dict(T=w.angle_samples, S=1, top_k=4, mode=lg.LG_BUCKETED, trace=False)
+    say("autotune: 600 mixed ligands, R=64, S=1")
+    before = dock_gpu(pocket, L, r32, a32, **kw)
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                           L.inv_bond_len, L.ref_point)
+    t, ms = lg.lg_autotune(pocket, dl, torch.from_numpy(r32).cuda(), torch.from_numpy(a32).cuda(), sweeps=1,
+                           top_k=4, trans_samples=w.angle_samples, trans_step=oracle.trans_step(w.angle_samples),
+                           clash_dist2=oracle.CLASH2)
+    kept = pocket.get_tuning()
+    assert bytes(kept) == bytes(t) and ms > 0
+    assert kept.use_graph == 1
+    after = dock_gpu(pocket, L, r32, a32, **kw)
+    for key in before:
+        np.testing.assert_array_equal(before[key], after[key], err_msg=f"tuned vs default: {key}")
+    say(f"autotune: {ms:.2f} ms, chunk {t.restart_chunk}, grid x{t.grid_scale}, "
+        f"waves/block {list(t.waves_per_block)}, lazy clash {t.lazy_clash}, "
+        f"{t.n_atom_clusters} x {t.n_rot_clusters} clusters")
+    pocket.free()
