@@ -77,8 +77,12 @@ typedef struct lg_pocket_s* lg_pocket;
  *   n                 number of ligands (0 is allowed: nothing to do)
  *   total_atoms       host value = atom_offset[n]
  *   total_torsions    host value = tors_offset[n]
- *   atom_offset_host  optional host copy of atom_offset; when NULL the library
- *   tors_offset_host  validates on the device (one small synchronous read-back)
+ *   atom_offset_host  optional host copies of the offsets, checked on the host
+ *   tors_offset_host  before any launch (sizes, limits, totals).  Every call also
+ *                     checks the device copies with one small kernel and a
+ *                     synchronous read-back of its counters (sizes, limits,
+ *                     consistency, local ids), so bad device data is reported
+ *                     as LG_ERR_INVALID_ARG / LG_ERR_LIMIT, never docked.
  * Limits: 1 <= atoms <= LG_MAX_ATOMS and 0 <= bonds <= LG_MAX_TORSIONS per
  * ligand; local ids in range. */
 typedef struct {
@@ -157,9 +161,11 @@ lg_status lg_free_pocket(lg_pocket pocket);
  * one kernel per ligand sized for the largest class; LG_BUCKETED classifies
  * ligands on the device by (atoms, bonds) into size buckets, docks every bucket
  * in one persistent launch of its class kernel pulling (ligand, restart) items
- * from a device queue, and replays the whole sequence as one HIP graph.
- * Workspace grows with R * total_atoms and is held by the pocket handle: calls
- * on one handle must not overlap. */
+ * from a device queue, and replays the whole sequence as one HIP graph.  Every
+ * restart records its final score and the selected sample of each scan; the
+ * kept poses are rebuilt from those records.  Workspace: 4 n R bytes of scores
+ * plus 2 R sweeps (6 n + total_torsions) bytes of records, held by the pocket
+ * handle: calls on one handle must not overlap. */
 lg_status lg_dock_batch(lg_pocket pocket, const lg_ligands* ligands, const lg_dock_params* params,
                         const lg_dock_out* out, void* stream);
 

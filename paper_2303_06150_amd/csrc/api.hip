@@ -22,8 +22,8 @@ hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const Gri
                               const DockDev& D, const QueueDev& Q, hipStream_t st);
 hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int tab_len, int* blocks_per_cu);
 hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr);
-hipError_t launch_topk(const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid, float* ox,
-                       float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st);
+hipError_t launch_topk(int nslot, const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid,
+                       float* ox, float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st);
 hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, float* score, float* grad,
                         hipStream_t st);
 hipError_t launch_rank_prep(const float* score, int n_groups, int group, float* keys, int32_t* vals,
@@ -398,7 +398,8 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   if (L->n > 0 && (!O->score || !O->restart_id || !O->x || !O->y || !O->z))
     return fail(LG_ERR_INVALID_ARG, "score, restart_id and x/y/z outputs are required");
   if (L->n == 0) return LG_OK;
-  if ((long long)P->restarts * L->total_atoms > (1LL << 40)) return fail(LG_ERR_LIMIT, "R * total_atoms too large");
+  if ((long long)P->restarts * P->sweeps * (6LL * L->n + L->total_torsions) > (1LL << 40))
+    return fail(LG_ERR_LIMIT, "R * sweeps * (6 n + total_torsions) move records too large");
   hipStream_t st = (hipStream_t)stream;
   LG_HIP(hipSetDevice(p->device));
 
@@ -408,8 +409,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   Layout lay;
   const size_t o_stats = lay.take(16 * sizeof(int32_t));
   const size_t o_final = lay.take((size_t)n * R * sizeof(float));
-  const size_t o_wp = lay.take((size_t)3 * R * L->total_atoms * sizeof(float));
-  const size_t o_piv = lay.take((size_t)3 * n * R * sizeof(float));
+  const size_t o_moves = lay.take((size_t)R * P->sweeps * (6 * (size_t)n + L->total_torsions) * sizeof(uint16_t));
   const size_t o_cls = lay.take((size_t)n * sizeof(int32_t));
   const size_t o_perm = lay.take((size_t)n * sizeof(int32_t));
   const size_t o_cnt = lay.take((size_t)(4 * B + 1) * sizeof(int32_t));
@@ -436,14 +436,12 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   D.restarts = P->restart_table;
   D.angles = P->angle_table;
   D.final_scores = (float*)(ws + o_final);
-  D.wpx = (float*)(ws + o_wp);
-  D.wpy = D.wpx + (size_t)R * L->total_atoms;
-  D.wpz = D.wpy + (size_t)R * L->total_atoms;
-  D.wpiv = (float*)(ws + o_piv);
+  D.moves = (uint16_t*)(ws + o_moves);
   D.lazy_clash = tu.lazy_clash;
   D.trace = O->trace;
   D.trace_w = 6 + (O->trace ? O->trace_kmax : 0);
   const lg::LigDev Lg = lig_dev(L);
+  const int topk_slots = std::max(1, (max_atoms + 63) / 64);   // replay instance for the largest ligand
   const int spl = spl_for(D.A, D.T);
   if (spl > 16) return fail(LG_ERR_LIMIT, "samples per lane %d > 16", spl);
 
@@ -452,7 +450,8 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
     const int nslot = LG_MAX_ATOMS / 64;
     for (int i = 0; i < n; ++i)
       LG_HIP(lg::launch_dock_plain(nslot, spl, tu.plain_waves_per_block, p->grid, Lg, D, i, st));
-    LG_HIP(lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, O->pivot, st));
+    LG_HIP(lg::launch_topk(topk_slots, Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores,
+                           O->pivot, st));
     return LG_OK;
   }
 
@@ -533,7 +532,9 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
       e = lg::launch_dock_bucket(b.slots, spl, b.waves_per_block, b.blocks, p->grid, Lg, D, Q, cs);
       if (e == hipSuccess && events) e = hipEventRecord(p->events[l + 1], cs);
     }
-    if (e == hipSuccess) e = lg::launch_topk(Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores, O->pivot, cs);
+    if (e == hipSuccess)
+      e = lg::launch_topk(topk_slots, Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores,
+                          O->pivot, cs);
     return e;
   };
 

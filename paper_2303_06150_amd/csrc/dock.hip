@@ -8,10 +8,15 @@
 // staged in LDS (broadcast reads), and accumulates nearest-voxel values
 // gathered from the L2-resident grid.  The pose lives in registers, atom
 // a = 64 s + lane in slot s < NSLOT.  The best sample comes from a DPP/readlane
-// reduction (lowest index among equal scores).  For torsions only the winning
-// sample is tested for clashes (lanes over the static atoms, loop over the
-// moving ones); a clashing winner is dropped and the next best taken, which
-// selects exactly the best admissible sample.
+// reduction (lowest index among equal scores).  Torsion samples are tested for
+// intramolecular clashes in the scoring pass against a pruned list of the
+// pairs that can clash at some angle.
+//
+// Outputs.  Each restart records its final score and the selected sample of
+// every scan (a few bytes per scan); the per-ligand top-k then rebuilds the k
+// kept poses by replaying their moves with the same apply functions the scans
+// use, so the poses are bit-identical to the docked ones without storing every
+// restart's coordinates.
 //
 // Arithmetic contract (matches the CPU oracle bit for bit): FP32, explicit
 // fmaf, no contraction; sums of quantised grid values are exact in any order,
@@ -82,6 +87,85 @@ __device__ __forceinline__ void pipelined_sum(int n, F gather, float (&acc)[NA],
   }
 }
 
+// ---- moves: the selected sample of a scan applied to the pose ----------------
+// Rotation by sample j about lab axis E through the pivot.
+template <int NSLOT, int E>
+__device__ __forceinline__ void apply_rot(const DockDev& D, PoseReg<NSLOT>& p, int j) {
+  constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
+  if (j == 0) return;
+  const float pP = p.piv[P], pQ = p.piv[Q];
+  const float c = D.angles[2 * j], sn = D.angles[2 * j + 1];
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    float vp = p.x[P][s] - pP, vq = p.x[Q][s] - pQ;
+    float np = fmaf(c, vp, -(sn * vq));
+    float nq = fmaf(sn, vp, c * vq);
+    p.x[P][s] = pP + np;
+    p.x[Q][s] = pQ + nq;
+  }
+}
+
+// Translation by sample j along lab axis E (the pivot moves along).
+template <int NSLOT, int E>
+__device__ __forceinline__ void apply_trans(const DockDev& D, PoseReg<NSLOT>& p, int j) {
+  if (j == 0) return;
+  const int m = j < D.T / 2 ? j : j - D.T;
+  const float dd = D.delta * (float)m;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) p.x[E][s] = p.x[E][s] + dd;
+  p.piv[E] = p.piv[E] + dd;
+}
+
+// Bond k's axis at the current pose: pivot atom a, unit direction u.
+struct BondAxis {
+  int a, b;
+  float xa, ya, za, ux, uy, uz;
+};
+
+template <int NSLOT>
+__device__ __forceinline__ BondAxis bond_axis(const LigDev& Lg, const PoseReg<NSLOT>& p, int toff, int k) {
+  BondAxis A;
+  A.a = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k)]);
+  A.b = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k) + 1]);
+  const float il = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Lg.inv_len[toff + k])));
+  A.xa = atom_value(p.x[0], A.a);
+  A.ya = atom_value(p.x[1], A.a);
+  A.za = atom_value(p.x[2], A.a);
+  const float xb = atom_value(p.x[0], A.b), yb = atom_value(p.x[1], A.b), zb = atom_value(p.x[2], A.b);
+  A.ux = (xb - A.xa) * il;
+  A.uy = (yb - A.ya) * il;
+  A.uz = (zb - A.za) * il;
+  return A;
+}
+
+// Rotation of the moving fragment of bond k (its atoms other than b) by the
+// matrix Mj about the axis through a.
+template <int NSLOT>
+__device__ __forceinline__ void apply_tors(PoseReg<NSLOT>& p, const BondAxis& A, const float (&Mj)[9],
+                                           const bool (&mv)[NSLOT]) {
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    if (mv[s]) {
+      float y0, y1, y2;
+      mat_apply(Mj, p.x[0][s] - A.xa, p.x[1][s] - A.ya, p.x[2][s] - A.za, y0, y1, y2);
+      p.x[0][s] = A.xa + y0;
+      p.x[1][s] = A.ya + y1;
+      p.x[2][s] = A.za + y2;
+    }
+  }
+}
+
+// Moving atoms of bond k held by this lane: in F_k, not the axis atom b.
+template <int NSLOT>
+__device__ __forceinline__ void moving_atoms(const uint32_t (&mk)[NSLOT], int N, int k, int b, bool (&mv)[NSLOT]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int at = s * 64 + lane;
+    mv[s] = at < N && ((mk[s] >> k) & 1u) && at != b;
+  }
+}
+
 // ---- rigid rotation scan about lab axis E through the pivot ------------------
 template <int NSLOT, int SPL, int E>
 __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr,
@@ -126,17 +210,7 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
   pipelined_sum<SPL>(N, gather, acc);
   if (lane == 0) acc[0] = s0;   // sample 0 is the current pose
   const int j = wave_argmax(acc, sm.valid_a);
-  if (j != 0) {
-    const float c = D.angles[2 * j], sn = D.angles[2 * j + 1];
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      float vp = p.x[P][s] - pP, vq = p.x[Q][s] - pQ;
-      float np = fmaf(c, vp, -(sn * vq));
-      float nq = fmaf(sn, vp, c * vq);
-      p.x[P][s] = pP + np;
-      p.x[Q][s] = pQ + nq;
-    }
-  }
+  apply_rot<NSLOT, E>(D, p, j);
   wave_sync();
   return j;
 }
@@ -176,13 +250,7 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
   };
   pipelined_sum<SPL>(N, gather, acc);
   const int j = wave_argmax(acc, sm.valid_t);
-  if (j != 0) {
-    const int m = j < D.T / 2 ? j : j - D.T;
-    const float dd = D.delta * (float)m;
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) p.x[E][s] = p.x[E][s] + dd;
-    p.piv[E] = p.piv[E] + dd;
-  }
+  apply_trans<NSLOT, E>(D, p, j);
   wave_sync();
   return j;
 }
@@ -202,12 +270,9 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
                          const SampleReg<SPL>& sm, const int* tab) {
   constexpr int PAIR_CAP = 128 * NSLOT;
   const int lane = lane_id();
-  const int a = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k)]);
-  const int b = __builtin_amdgcn_readfirstlane(Lg.tors_atoms[2 * (toff + k) + 1]);
-  const float il = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Lg.inv_len[toff + k])));
-  const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
-  const float xb = atom_value(p.x[0], b), yb = atom_value(p.x[1], b), zb = atom_value(p.x[2], b);
-  const float ux = (xb - xa) * il, uy = (yb - ya) * il, uz = (zb - za) * il;
+  const BondAxis A = bond_axis(Lg, p, toff, k);
+  const int a = A.a, b = A.b;
+  const float xa = A.xa, ya = A.ya, za = A.za, ux = A.ux, uy = A.uy, uz = A.uz;
 
   // moving atoms of F_k other than b, compacted into scr; their current score;
   // axial position h and radius r of every static atom about the bond axis
@@ -215,12 +280,12 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
   float hs[NSLOT], rs[NSLOT];
   int m = 0;
   float s0 = 0.f;
+  moving_atoms(mk, N, k, b, mv);
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const int at = s * 64 + lane;
     const bool in = at < N;
     const bool inf = in && ((mk[s] >> k) & 1u);
-    mv[s] = inf && at != b;
     st[s] = in && !inf && at != a;
     const float vx = p.x[0][s] - xa, vy = p.x[1][s] - ya, vz = p.x[2][s] - za;
     hs[s] = vx * ux + vy * uy + vz * uz;
@@ -345,18 +410,7 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
       wave_sync();
     }
   }
-  if (j != 0) {
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      if (mv[s]) {
-        float y0, y1, y2;
-        mat_apply(Mj, p.x[0][s] - xa, p.x[1][s] - ya, p.x[2][s] - za, y0, y1, y2);
-        p.x[0][s] = xa + y0;
-        p.x[1][s] = ya + y1;
-        p.x[2][s] = za + y2;
-      }
-    }
-  }
+  if (j != 0) apply_tors(p, A, Mj, mv);
   wave_sync();
   return j;
 }
@@ -415,13 +469,9 @@ __device__ void load_ligand(const LigDev& Lg, int lig, LigReg<NSLOT>& L) {
   for (int c = 0; c < 3; ++c) L.P0[c] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Lg.ref[3 * lig + c])));
 }
 
-// One restart: placement, S sweeps, final trilinear score, outputs.
-template <int NSLOT, int SPL>
-__device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& D, const SampleReg<SPL>& sm,
-                             const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand, const int* tab) {
-  const int lane = lane_id();
-  const int N = L.N;
-  PoseReg<NSLOT> p;
+// Restart placement: x = M_r (x0 - P0) + (c + t_r), pivot c + t_r.
+template <int NSLOT>
+__device__ __forceinline__ void place_pose(const DockDev& D, const LigReg<NSLOT>& L, int r, PoseReg<NSLOT>& p) {
   const float* row = D.restarts + 12 * r;
   float m[12];
 #pragma unroll
@@ -437,8 +487,24 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
     }
   }
   p.piv[0] = q[0]; p.piv[1] = q[1]; p.piv[2] = q[2];
+}
+
+// Selected samples of restart r of a ligand: S rows of 6 + K entries.
+__device__ __forceinline__ uint16_t* move_record(const DockDev& D, int lig, int toff, int K, int r) {
+  return D.moves + (size_t)D.R * D.S * (6 * (size_t)lig + toff) + (size_t)r * D.S * (6 + K);
+}
+
+// One restart: placement, S sweeps, final trilinear score, outputs.
+template <int NSLOT, int SPL>
+__device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& D, const SampleReg<SPL>& sm,
+                             const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand, const int* tab) {
+  const int lane = lane_id();
+  const int N = L.N;
+  PoseReg<NSLOT> p;
+  place_pose(D, L, r, p);
 
   int16_t* tr = D.trace ? D.trace + ((size_t)lig * D.R + r) * (size_t)D.S * D.trace_w : nullptr;
+  uint16_t* mrec = move_record(D, lig, L.toff, L.K, r);
   for (int sw = 0; sw < D.S; ++sw) {
     int jr0 = rot_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm, tab);
     int jr1 = rot_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm, tab);
@@ -447,12 +513,18 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
     int jt1 = trans_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm, tab);
     int jt2 = trans_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm, tab);
     int16_t* trow = tr ? tr + (size_t)sw * D.trace_w : nullptr;
+    uint16_t* mrow = mrec + (size_t)sw * (6 + L.K);
+    if (lane == 0) {
+      mrow[0] = (uint16_t)jr0; mrow[1] = (uint16_t)jr1; mrow[2] = (uint16_t)jr2;
+      mrow[3] = (uint16_t)jt0; mrow[4] = (uint16_t)jt1; mrow[5] = (uint16_t)jt2;
+    }
     if (trow && lane == 0) {
       trow[0] = (int16_t)jr0; trow[1] = (int16_t)jr1; trow[2] = (int16_t)jr2;
       trow[3] = (int16_t)jt0; trow[4] = (int16_t)jt1; trow[5] = (int16_t)jt2;
     }
     for (int k = 0; k < L.K; ++k) {
       int jk = tors_scan<NSLOT, SPL>(G, Lg, D, p, N, L.toff, k, L.mk, scr, cand, sm, tab);
+      if (lane == 0) mrow[6 + k] = (uint16_t)jk;
       if (trow && lane == 0) trow[6 + k] = (int16_t)jk;
     }
   }
@@ -469,18 +541,37 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
     for (int l = 0; l < cnt; ++l) total = total + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[s]), l));
   }
   if (lane == 0) D.final_scores[(size_t)lig * D.R + r] = total;
-  const size_t base = (size_t)L.abase * D.R + (size_t)r * N;
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const int a = s * 64 + lane;
-    if (a < N) {
-      D.wpx[base + a] = p.x[0][s];
-      D.wpy[base + a] = p.x[1][s];
-      D.wpz[base + a] = p.x[2][s];
+}
+
+// The pose of restart r after its recorded moves: placement, then every
+// sweep's rotations, translations and torsions with the selected samples.
+template <int NSLOT>
+__device__ void replay_restart(const LigDev& Lg, const DockDev& D, const LigReg<NSLOT>& L, int lig, int r,
+                               PoseReg<NSLOT>& p) {
+  place_pose(D, L, r, p);
+  const uint16_t* mrec = move_record(D, lig, L.toff, L.K, r);
+  // recorded indices are below A (rotations, torsions) and T (translations); the
+  // clamps only keep table reads in range
+  const int amax = D.A - 1, tmax = D.T - 1;
+  for (int sw = 0; sw < D.S; ++sw) {
+    const uint16_t* mrow = mrec + (size_t)sw * (6 + L.K);
+    apply_rot<NSLOT, 0>(D, p, min((int)__builtin_amdgcn_readfirstlane(mrow[0]), amax));
+    apply_rot<NSLOT, 1>(D, p, min((int)__builtin_amdgcn_readfirstlane(mrow[1]), amax));
+    apply_rot<NSLOT, 2>(D, p, min((int)__builtin_amdgcn_readfirstlane(mrow[2]), amax));
+    apply_trans<NSLOT, 0>(D, p, min((int)__builtin_amdgcn_readfirstlane(mrow[3]), tmax));
+    apply_trans<NSLOT, 1>(D, p, min((int)__builtin_amdgcn_readfirstlane(mrow[4]), tmax));
+    apply_trans<NSLOT, 2>(D, p, min((int)__builtin_amdgcn_readfirstlane(mrow[5]), tmax));
+    for (int k = 0; k < L.K; ++k) {
+      const int j = min((int)__builtin_amdgcn_readfirstlane(mrow[6 + k]), amax);
+      if (j == 0) continue;
+      const BondAxis A = bond_axis(Lg, p, L.toff, k);
+      float Mj[9];
+      torsion_matrix(A.ux, A.uy, A.uz, D.angles[2 * j], D.angles[2 * j + 1], Mj);
+      bool mv[NSLOT];
+      moving_atoms(L.mk, L.N, k, A.b, mv);
+      apply_tors(p, A, Mj, mv);
     }
   }
-  const float pv = lane == 0 ? p.piv[0] : lane == 1 ? p.piv[1] : p.piv[2];
-  if (lane < 3) D.wpiv[((size_t)lig * D.R + r) * 3 + lane] = pv;
 }
 
 // Plain method: one launch per ligand; wavefront w of the grid docks restart w.
@@ -549,8 +640,10 @@ __global__ __launch_bounds__(256) void dock_bucket_kernel(GridDev G, LigDev Lg, 
   }
 }
 
-// Per-ligand top-k over restarts (score descending, equal scores: lower r), and
-// the copy of the selected poses.  One wavefront per ligand.
+// Per-ligand top-k over restarts (score descending, equal scores: lower r);
+// the kept poses and pivots rebuilt from their recorded moves.  One wavefront
+// per ligand.
+template <int NSLOT>
 __global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, int k, float* score,
                                                     int32_t* rid, float* ox, float* oy, float* oz,
                                                     float* all_scores, float* opiv) {
@@ -560,8 +653,9 @@ __global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, 
   const float* fs = D.final_scores + (size_t)lig * D.R;
   if (all_scores)
     for (int r = lane; r < D.R; r += 64) all_scores[(size_t)lig * D.R + r] = fs[r];
-  const int abase = Lg.atom_offset[lig];
-  const int N = Lg.atom_offset[lig + 1] - abase;
+  LigReg<NSLOT> L;
+  load_ligand(Lg, lig, L);
+  if (L.N > 64 * NSLOT) return;   // cannot happen: the instance is sized for the largest ligand
   int pk = INT_MAX, pr = -1;   // previous selection (key, r)
   for (int qi = 0; qi < k; ++qi) {
     int best = INT_MIN, br = INT_MAX;
@@ -578,14 +672,20 @@ __global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, 
       score[(size_t)lig * k + qi] = fs[rs];
       rid[(size_t)lig * k + qi] = rs;
     }
-    if (opiv && lane < 3) opiv[((size_t)lig * k + qi) * 3 + lane] = D.wpiv[((size_t)lig * D.R + rs) * 3 + lane];
-    const size_t src = (size_t)abase * D.R + (size_t)rs * N;
-    const size_t dst = (size_t)k * abase + (size_t)qi * N;
-    for (int a = lane; a < N; a += 64) {
-      ox[dst + a] = D.wpx[src + a];
-      oy[dst + a] = D.wpy[src + a];
-      oz[dst + a] = D.wpz[src + a];
+    PoseReg<NSLOT> p;
+    replay_restart(Lg, D, L, lig, rs, p);
+    const size_t dst = (size_t)k * L.abase + (size_t)qi * L.N;
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s) {
+      const int a = s * 64 + lane;
+      if (a < L.N) {
+        ox[dst + a] = p.x[0][s];
+        oy[dst + a] = p.x[1][s];
+        oz[dst + a] = p.x[2][s];
+      }
     }
+    const float pv = lane == 0 ? p.piv[0] : lane == 1 ? p.piv[1] : p.piv[2];
+    if (opiv && lane < 3) opiv[((size_t)lig * k + qi) * 3 + lane] = pv;
   }
 }
 
@@ -651,12 +751,18 @@ hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr) {
 #undef CALL
 }
 
-hipError_t launch_topk(const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid, float* ox,
-                       float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st) {
+hipError_t launch_topk(int nslot, const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid,
+                       float* ox, float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const int wpb = 4;
-  hipLaunchKernelGGL(topk_kernel, dim3((n + wpb - 1) / wpb), dim3(64 * wpb), 0, st, Lg, D, n, k, score, rid, ox,
-                     oy, oz, all_scores, pivot);
+  const dim3 grid((n + wpb - 1) / wpb), block(64 * wpb);
+  switch (nslot) {
+    case 1: hipLaunchKernelGGL(topk_kernel<1>, grid, block, 0, st, Lg, D, n, k, score, rid, ox, oy, oz, all_scores, pivot); break;
+    case 2: hipLaunchKernelGGL(topk_kernel<2>, grid, block, 0, st, Lg, D, n, k, score, rid, ox, oy, oz, all_scores, pivot); break;
+    case 3: hipLaunchKernelGGL(topk_kernel<3>, grid, block, 0, st, Lg, D, n, k, score, rid, ox, oy, oz, all_scores, pivot); break;
+    case 4: hipLaunchKernelGGL(topk_kernel<4>, grid, block, 0, st, Lg, D, n, k, score, rid, ox, oy, oz, all_scores, pivot); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -56,10 +56,8 @@ struct DockDev {
   const float* restarts;   // [R][12]
   const float* angles;     // [A][2]
   float* final_scores;     // [n*R]
-  float* wpx;              // [R*total_atoms], ligand i restart r atom a at atom_offset[i]*R + r*N + a
-  float* wpy;
-  float* wpz;
-  float* wpiv;             // [n*R*3] pivot of each restart's final pose
+  uint16_t* moves;         // [R*S*(6n + total_torsions)]: selected sample of every scan;
+                           // ligand i restart r sweep s at R*S*(6i + tors_offset[i]) + (r*S + s)*(6 + K_i)
   int16_t* trace;          // optional [n][R][S][trace_w]
   int trace_w;
 };

@@ -83,11 +83,25 @@ __device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int
   }
 }
 
+// Per-atom columns summed in atom order through an LDS tile: the wavefront
+// writes the columns of 64 atoms (one slot) as tile[column * TILE_STRIDE + lane],
+// then lane c adds column c's values atom by atom.  Each column's sum runs
+// over atoms 0..N-1 in order, like a sequential loop, but all columns at once.
+constexpr int TILE_COLS = 16;                      // LDS per wavefront stays small (occupancy)
+constexpr int TILE_STRIDE = 65;                    // odd stride: conflict-free rows and columns
+constexpr int TILE_FLOATS = TILE_COLS * TILE_STRIDE;
+constexpr int GRAD_COLS = 7 + 3 * 32;              // score, force, torque, 3 per bond
+constexpr int GRAD_RES_FLOATS = 104;               // GRAD_COLS rounded up to float4
+constexpr int GRAD_LDS_FLOAT4 = (TILE_FLOATS + GRAD_RES_FLOATS) / 4;
+
 // Trilinear score and its gradient with respect to the local move at zero;
-// sums in atom order.  g_out: t[3], w[3], then theta[K] into th_grad.
+// sums in atom order.  g_out: t[3], w[3], then theta[K] into th_grad.  Column
+// 0 is the score, 1..3 the force, 4..6 the torque about the pivot, 7 + 3k + d
+// component d of bond k's torque about its pivot atom over F_k.
 template <int NSLOT>
 __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N,
-                               int K, const int2* tors, const float* inv_len, float* g_out, float* th_grad) {
+                               int K, const int2* tors, const float* inv_len, float* g_out, float* th_grad,
+                               float* tile, float* res) {
   const int lane = lane_id();
   float v[NSLOT], g[3][NSLOT];
 #pragma unroll
@@ -96,66 +110,96 @@ __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, cons
     v[s] = (s * 64 + lane < N) ? trilinear(G, p.x[0][s], p.x[1][s], p.x[2][s], gg) : 0.f;
     g[0][s] = gg[0]; g[1][s] = gg[1]; g[2][s] = gg[2];
   }
-  const float score = atom_order_sum(v, N);
-  float tq[3][NSLOT];
+  // column chunks: the 7 pose columns with bonds 0..2, then 5 bonds per chunk
+  for (int k0 = 0, first = 1; first || k0 < K; first = 0) {
+    const int base = first ? 7 : 0;
+    const int nb = min(K - k0, (TILE_COLS - base) / 3);
+    const int ncol = base + 3 * nb;
+    const int col0 = first ? 0 : 7 + 3 * k0;
+    float acc = 0.f;
 #pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const float r0 = p.x[0][s] - p.piv[0], r1 = p.x[1][s] - p.piv[1], r2 = p.x[2][s] - p.piv[2];
-    tq[0][s] = r1 * g[2][s] - r2 * g[1][s];
-    tq[1][s] = r2 * g[0][s] - r0 * g[2][s];
-    tq[2][s] = r0 * g[1][s] - r1 * g[0][s];
+    for (int s = 0; s < NSLOT; ++s) {
+      const int cnt = min(64, N - s * 64);
+      if (cnt <= 0) break;
+      if (first) {
+        const float r0 = p.x[0][s] - p.piv[0], r1 = p.x[1][s] - p.piv[1], r2 = p.x[2][s] - p.piv[2];
+        tile[0 * TILE_STRIDE + lane] = v[s];
+        tile[1 * TILE_STRIDE + lane] = g[0][s];
+        tile[2 * TILE_STRIDE + lane] = g[1][s];
+        tile[3 * TILE_STRIDE + lane] = g[2][s];
+        tile[4 * TILE_STRIDE + lane] = r1 * g[2][s] - r2 * g[1][s];
+        tile[5 * TILE_STRIDE + lane] = r2 * g[0][s] - r0 * g[2][s];
+        tile[6 * TILE_STRIDE + lane] = r0 * g[1][s] - r1 * g[0][s];
+      }
+      for (int kk = 0; kk < nb; ++kk) {
+        const int k = k0 + kk;
+        const int a = tors[k].x;
+        const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
+        const bool in = (mk[s] >> k) & 1u;
+        const float r0 = p.x[0][s] - xa, r1 = p.x[1][s] - ya, r2 = p.x[2][s] - za;
+        float* t = tile + (base + 3 * kk) * TILE_STRIDE + lane;
+        t[0] = in ? r1 * g[2][s] - r2 * g[1][s] : 0.f;
+        t[TILE_STRIDE] = in ? r2 * g[0][s] - r0 * g[2][s] : 0.f;
+        t[2 * TILE_STRIDE] = in ? r0 * g[1][s] - r1 * g[0][s] : 0.f;
+      }
+      wave_sync();
+      if (lane < ncol) {
+        const float* col = tile + lane * TILE_STRIDE;
+        for (int l = 0; l < cnt; ++l) acc = acc + col[l];
+      }
+      wave_sync();
+    }
+    if (lane < ncol) res[col0 + lane] = acc;
+    k0 += nb;
   }
-  for (int d = 0; d < 3; ++d) {
-    g_out[d] = atom_order_sum(g[d], N);
-    g_out[3 + d] = atom_order_sum(tq[d], N);
-  }
+  wave_sync();
+#pragma unroll
+  for (int d = 0; d < 6; ++d) g_out[d] = res[1 + d];
   for (int k = 0; k < K; ++k) {
     const int a = tors[k].x, b = tors[k].y;
     const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
     const float il = inv_len[k];
     const float ux = (atom_value(p.x[0], b) - xa) * il, uy = (atom_value(p.x[1], b) - ya) * il,
                 uz = (atom_value(p.x[2], b) - za) * il;
-    float t[3][NSLOT];
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      const bool in = (mk[s] >> k) & 1u;
-      const float r0 = p.x[0][s] - xa, r1 = p.x[1][s] - ya, r2 = p.x[2][s] - za;
-      t[0][s] = in ? r1 * g[2][s] - r2 * g[1][s] : 0.f;
-      t[1][s] = in ? r2 * g[0][s] - r0 * g[2][s] : 0.f;
-      t[2][s] = in ? r0 * g[1][s] - r1 * g[0][s] : 0.f;
-    }
-    const float t0 = atom_order_sum(t[0], N), t1 = atom_order_sum(t[1], N), t2 = atom_order_sum(t[2], N);
-    if (lane == 0) th_grad[k] = ux * t0 + uy * t1 + uz * t2;
+    const float* t = res + 7 + 3 * k;
+    if (lane == 0) th_grad[k] = ux * t[0] + uy * t[1] + uz * t[2];
   }
-  return score;
+  return res[0];
 }
 
 // Refinement clash rule: every pair that some bond's torsion moves -- exactly one
 // of the two in F_k, the moving one not b_k, the other not a_k -- at squared
-// distance >= clash2.  `pos` holds the pose (xyz, mask bits in w) in LDS.
+// distance >= clash2.  `pos` holds the pose (xyz, mask bits in w) in LDS.  Each
+// unordered pair is visited once: the lane's atom i with atom (i + d) mod N for
+// d = 1 .. N/2 (for even N the pair at d = N/2 only from its lower end).  The
+// distance test comes first; the bond rule is evaluated only for pairs inside
+// the clash distance, which are few (bonded neighbours).
 template <int NSLOT>
 __device__ bool move_clash_free(const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N,
                                 const int2* tors, const float4* pos, float clash2) {
   const int lane = lane_id();
   bool clash = false;
-  for (int j = 0; j < N; ++j) {
-    const float4 pj = pos[j];
-    const uint32_t mj = __float_as_uint(pj.w);
+  const int half = N >> 1;
+  for (int d = 1; d <= half; ++d) {
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
+      if (s * 64 >= N) break;
       const int i = s * 64 + lane;
-      const uint32_t diff = mk[s] ^ mj;
-      if (i >= N || j <= i || diff == 0u) continue;
+      int j = i + d;
+      if (j >= N) j -= N;
+      if (i >= N || (2 * d == N && i >= d)) continue;
+      const float4 pj = pos[j];
+      const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
+      if (!(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2)) continue;
+      const uint32_t mj = __float_as_uint(pj.w);
       bool changes = false;
-      for (uint32_t d = diff; d != 0u && !changes; d &= d - 1u) {
-        const int k = __builtin_ctz(d);
+      for (uint32_t m = mk[s] ^ mj; m != 0u && !changes; m &= m - 1u) {
+        const int k = __builtin_ctz(m);
         const int mover = ((mk[s] >> k) & 1u) ? i : j;
         const int other = mover == i ? j : i;
         changes = mover != tors[k].y && other != tors[k].x;
       }
-      if (!changes) continue;
-      const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
-      if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2) clash = true;
+      clash |= changes;
     }
   }
   return !wave_any(clash);
@@ -165,10 +209,12 @@ template <int NSLOT>
 __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, RefineDev Rp, int n) {
   extern __shared__ float4 lds[];
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
-  float4* pos = lds + (size_t)wave * (64 * NSLOT + 32);
+  float4* pos = lds + (size_t)wave * (64 * NSLOT + 32 + GRAD_LDS_FLOAT4);
   int2* tors = reinterpret_cast<int2*>(pos + 64 * NSLOT);     // 32 entries (16 float4)
   float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries (8 float4)
   float* th = inv_len + 32;                                   // 32 bond gradients / steps (8 float4)
+  float* tile = th + 32;                                      // column sums of the gradient
+  float* res = tile + TILE_FLOATS;
   const int i = blockIdx.x * nwaves + wave;   // pose: member i % kpl of ligand i / kpl
   if (i >= n) return;
   const int lig = i / Rp.kpl, member = i - lig * Rp.kpl;
@@ -203,7 +249,7 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   float scale = 1.f;
   float g[6];
   for (int step = 0; step < Rp.steps; ++step) {
-    move_gradient(G, cur, mk, N, K, tors, inv_len, g, th);
+    move_gradient(G, cur, mk, N, K, tors, inv_len, g, th, tile, res);
     wave_sync();
     float q[6];
     float dt[3], dw[3];
@@ -269,10 +315,12 @@ __global__ __launch_bounds__(256) void score_moves_kernel(GridDev G, LigDev P, c
                                                           float* score, float* grad) {
   extern __shared__ float4 lds[];
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
-  float4* base = lds + (size_t)wave * 32;
+  float4* base = lds + (size_t)wave * (32 + GRAD_LDS_FLOAT4);
   int2* tors = reinterpret_cast<int2*>(base);                 // 32 entries
   float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries
   float* th = inv_len + 32;                                   // 32 entries
+  float* tile = th + 32;
+  float* res = tile + TILE_FLOATS;
   const int i = blockIdx.x * nwaves + wave;
   if (i >= n) return;
   const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[i]);
@@ -305,7 +353,7 @@ __global__ __launch_bounds__(256) void score_moves_kernel(GridDev G, LigDev P, c
   apply_move<NSLOT, true>(p, mk, N, K, tors, inv_len, q, th);
   float g[6];
   wave_sync();
-  const float sc = move_gradient(G, p, mk, N, K, tors, inv_len, g, th);
+  const float sc = move_gradient(G, p, mk, N, K, tors, inv_len, g, th, tile, res);
   wave_sync();
   if (lane == 0) score[i] = sc;
   if (!grad) return;
@@ -343,7 +391,7 @@ hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, cons
   if (n == 0) return hipSuccess;
   const int wpb = 4;
   const dim3 grid((n + wpb - 1) / wpb), block(64 * wpb);
-  const size_t lds = (size_t)wpb * 32 * sizeof(float4);
+  const size_t lds = (size_t)wpb * (32 + GRAD_LDS_FLOAT4) * sizeof(float4);
   switch (nslot) {
     case 1: hipLaunchKernelGGL(score_moves_kernel<1>, grid, block, lds, st, G, P, moves, n, score, grad); break;
     case 2: hipLaunchKernelGGL(score_moves_kernel<2>, grid, block, lds, st, G, P, moves, n, score, grad); break;
@@ -354,7 +402,9 @@ hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, cons
   return hipGetLastError();
 }
 
-static size_t refine_lds(int nslot, int wpb) { return (size_t)wpb * (64 * nslot + 32) * sizeof(float4); }
+static size_t refine_lds(int nslot, int wpb) {
+  return (size_t)wpb * (64 * nslot + 32 + GRAD_LDS_FLOAT4) * sizeof(float4);
+}
 
 hipError_t launch_refine(int nslot, const GridDev& G, const LigDev& P, const RefineDev& Rp, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;
