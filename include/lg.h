@@ -238,8 +238,8 @@ typedef struct {
   int32_t grid_scale;             /* 1..64 */
   int32_t plain_waves_per_block;  /* 1, 2 or 4 */
   int32_t use_graph;              /* 1: capture once and replay as a HIP graph; 0: launch
-                                     directly on the caller's stream with timing events
-                                     between the bucket launches */
+                                     directly, with timing events around the bucket
+                                     launches */
   int32_t lazy_clash;             /* 0: decide every torsion sample's clash test in the
                                      scoring pass (pruned pair list); 1: test only the
                                      winner and drop it while it clashes */
@@ -258,17 +258,21 @@ lg_status lg_get_tuning(lg_pocket pocket, lg_tuning* tuning);
  * test variant.  Times are the bucket launches of one call (events between
  * launches), best of two.  On success the handle keeps the best tuning (its
  * use_graph setting unchanged), *out receives it and *best_ms (optional) its
- * time; on failure the handle's tuning is restored.  Results never depend on
+ * time (span of the bucket launches); on failure the handle's tuning is
+ * restored.  Results never depend on
  * the tuning.  Synchronises `stream`; allocates its trial outputs. */
 lg_status lg_autotune(lg_pocket pocket, const lg_ligands* ligands, const lg_dock_params* params, int32_t passes,
                       lg_tuning* out, float* best_ms, void* stream);
 
 /* Per-bucket report of the last LG_BUCKETED call on a handle -- the MI355X
  * analog of the paper's Table 1 (registers and resident blocks per size class)
- * plus the launch duration, measured with events recorded in the graph around
- * each bucket's launch.  Fills up to `capacity` entries (NULL: none) and returns
- * the number of bucket launches, or a negative lg_status.  Synchronises the
- * device to read ligand counts and durations. */
+ * plus durations when the call ran with use_graph = 0 (events around every
+ * launch).  Bucket launches run concurrently (the first on the caller's stream,
+ * the others on up to three library streams, joined before the top-k), largest
+ * instance first, so their durations overlap; span_ms covers all of them.
+ * Fills up to `capacity` entries (NULL: none) and returns the number of bucket
+ * launches, or a negative lg_status.  Synchronises the device to read ligand
+ * counts and durations. */
 typedef struct {
   int32_t bucket;            /* atom cluster * n_rot_clusters + rotamer cluster */
   int32_t atom_bound;        /* atoms <= atom_bound */
@@ -282,6 +286,7 @@ typedef struct {
   int32_t blocks;            /* persistent grid of the launch */
   int32_t ligands;           /* ligands in the bucket */
   float ms;                  /* launch duration, -1 if unknown */
+  float span_ms;             /* first launch start to last launch end, -1 if unknown */
 } lg_bucket_stat;
 
 int32_t lg_bucket_stats(lg_pocket pocket, lg_bucket_stat* out, int32_t capacity);

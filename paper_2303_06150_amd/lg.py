@@ -82,7 +82,7 @@ class lg_bucket_stat(ctypes.Structure):
     _fields_ = [("bucket", c_int32), ("atom_bound", c_int32), ("rot_bound", c_int32), ("slots", c_int32),
                 ("samples_per_lane", c_int32), ("waves_per_block", c_int32), ("vgprs", c_int32),
                 ("lds_bytes", c_int32), ("blocks_per_cu", c_int32), ("blocks", c_int32), ("ligands", c_int32),
-                ("ms", c_float)]
+                ("ms", c_float), ("span_ms", c_float)]
 
 
 _lib = None
@@ -256,7 +256,7 @@ class Pocket:
 
     def bucket_stats(self) -> list:
         """lg_bucket_stats of the last bucketed call, as dicts."""
-        cap = 64
+        cap = 512
         buf = (lg_bucket_stat * cap)()
         n = _lib.lg_bucket_stats(self.handle, buf, cap)
         if n < 0:
