@@ -82,8 +82,8 @@ def bucket_of(n_atoms, n_tors, tuning):
 
 
 def read_traffic(kernel_tag):
-    """HBM traffic per dispatch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+    """HBM traffic of one step's bucket launches from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -258,13 +258,12 @@ def main():
         dom_ms = float(np.mean(bucket_ms[dom["bucket"]]))
         dom_ops = float(ops[bid == dom["bucket"]].sum())
         kernel = f"dock_bucket_kernel<{dom['slots']},{dom['samples_per_lane']}>"
-        kernel_tag = f"dock_bucket_s{dom['slots']}_spl{dom['samples_per_lane']}_{args.workload}"
-        traffic = read_traffic(kernel_tag)
     else:
         dom_ms = float(stats[0]["span_ms"])
         dom_ops = float(ops.sum())
         kernel = " + ".join(f"dock_bucket_kernel<{b['slots']},{b['samples_per_lane']}>" for b in busy) + " (concurrent)"
-        traffic = None
+    # HBM bytes of one step's bucket launches (all buckets), measured on this source
+    traffic = read_traffic(f"dock_buckets_{args.workload}")
     achieved = dom_ops / (dom_ms * 1e-3)
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(PEAK_LANE_OPS / 1e12, 3),
                     unit="TOP/s", frac=round(achieved / PEAK_LANE_OPS, 4), traffic=traffic, kernel=kernel,
