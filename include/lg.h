@@ -169,6 +169,47 @@ lg_status lg_free_pocket(lg_pocket pocket);
 lg_status lg_dock_batch(lg_pocket pocket, const lg_ligands* ligands, const lg_dock_params* params,
                         const lg_dock_out* out, void* stream);
 
+/* A library held in host memory: the lg_ligands layout with every array a
+ * host pointer (no device copy needed). */
+typedef struct {
+  int32_t n;
+  int32_t total_atoms;
+  int32_t total_torsions;
+  const int32_t* atom_offset;      /* host [n+1] */
+  const int32_t* tors_offset;      /* host [n+1] */
+  const float* x;                  /* host [total_atoms] */
+  const float* y;
+  const float* z;
+  const uint32_t* frag_mask;       /* host [total_atoms] */
+  const int32_t* tors_atoms;       /* host [2*total_torsions] */
+  const float* inv_bond_len;       /* host [total_torsions] */
+  const float* ref_point;          /* host [3n] */
+} lg_host_ligands;
+
+/* Host outputs of lg_dock_stream, in the lg_dock_out layout (pivot optional). */
+typedef struct {
+  float* score;                    /* host [n*top_k] */
+  int32_t* restart_id;             /* host [n*top_k] */
+  float* x;                        /* host [top_k*total_atoms] */
+  float* y;
+  float* z;
+  float* pivot;                    /* host [n*top_k*3] or NULL */
+} lg_host_out;
+
+/* Dock a library held in host memory, streamed through the device in chunks of
+ * at most `chunk` consecutive ligands -- the worker / double-buffer structure of
+ * Sec. 2 on one GPU: while chunk c docks on `stream` (bucketed, launched
+ * directly), chunk c+1's inputs are packed into pinned staging and copied in on
+ * a copy stream and chunk c-1's results copied back on another, two buffer
+ * slots alternating.  Device memory is bounded by the chunk (two slots plus the
+ * docking workspace of one chunk), not by the library.  The library is
+ * validated on the host first (same rules as lg_dock_batch's device check).
+ * Results are those of lg_dock_batch on the whole library in LG_BUCKETED mode;
+ * params' tables are device memory.  Returns when every result is in `out`.
+ * Calls on one handle must not overlap. */
+lg_status lg_dock_stream(lg_pocket pocket, const lg_host_ligands* ligands, const lg_dock_params* params,
+                         int32_t chunk, const lg_host_out* out, void* stream);
+
 /* Score poses (Sec. 2 "evaluate the interaction strength", "rank").  Each
  * ligand of `poses` is one pose.  interp = LG_NEAREST or LG_TRILINEAR; score[i]
  * = sum over its atoms in atom order.  grad (optional, trilinear only): per

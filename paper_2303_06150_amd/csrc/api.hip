@@ -392,8 +392,32 @@ lg_status lg_get_tuning(lg_pocket p, lg_tuning* t) {
   return LG_OK;
 }
 
-lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* P, const lg_dock_out* O,
-                        void* stream) {
+}  // extern "C"
+
+// Workspace of one docking call: validation counters, final scores, move
+// records, bucket arrays.
+struct DockWs {
+  size_t stats, final_scores, moves, cls, perm, cnt, bytes;
+};
+
+DockWs dock_ws_layout(int n, int R, int S, long long total_torsions, int buckets) {
+  Layout lay;
+  DockWs w;
+  w.stats = lay.take(16 * sizeof(int32_t));
+  w.final_scores = lay.take((size_t)n * R * sizeof(float));
+  w.moves = lay.take((size_t)R * S * (6 * (size_t)n + (size_t)total_torsions) * sizeof(uint16_t));
+  w.cls = lay.take((size_t)n * sizeof(int32_t));
+  w.perm = lay.take((size_t)n * sizeof(int32_t));
+  w.cnt = lay.take((size_t)(4 * buckets + 1) * sizeof(int32_t));
+  w.bytes = lay.off;
+  return w;
+}
+
+// Docking of one batch.  host_max_atoms >= 0: the batch was validated on the
+// host (largest ligand and bond count given), no device check and read-back;
+// direct: launch on the stream even when the tuning asks for a graph.
+lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params* P, const lg_dock_out* O,
+                          void* stream, int host_max_atoms, int host_max_tors, bool direct) {
   if (!p || !P || !O) return fail(LG_ERR_INVALID_ARG, "pocket, params and out must not be NULL");
   lg_status s = check_ligands(L, true);
   if (s != LG_OK) return s;
@@ -416,21 +440,18 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   const int n = L->n, R = P->restarts;
   const lg_tuning& tu = p->tuning;
   const int B = tu.n_atom_clusters * tu.n_rot_clusters;
-  Layout lay;
-  const size_t o_stats = lay.take(16 * sizeof(int32_t));
-  const size_t o_final = lay.take((size_t)n * R * sizeof(float));
-  const size_t o_moves = lay.take((size_t)R * P->sweeps * (6 * (size_t)n + L->total_torsions) * sizeof(uint16_t));
-  const size_t o_cls = lay.take((size_t)n * sizeof(int32_t));
-  const size_t o_perm = lay.take((size_t)n * sizeof(int32_t));
-  const size_t o_cnt = lay.take((size_t)(4 * B + 1) * sizeof(int32_t));
-  s = ensure_ws(p, lay.off);
+  const DockWs wl = dock_ws_layout(n, R, P->sweeps, L->total_torsions, B);
+  const size_t o_final = wl.final_scores, o_moves = wl.moves, o_cls = wl.cls, o_perm = wl.perm, o_cnt = wl.cnt;
+  s = ensure_ws(p, wl.bytes);
   if (s != LG_OK) return s;
   char* ws = (char*)p->ws;
-  int32_t* stats = (int32_t*)(ws + o_stats);
+  int32_t* stats = (int32_t*)(ws + wl.stats);
 
-  int max_atoms = 0, max_tors = 0;
-  s = check_on_device(p, L, stats, st, &max_atoms, &max_tors);
-  if (s != LG_OK) return s;
+  int max_atoms = host_max_atoms, max_tors = host_max_tors;
+  if (host_max_atoms < 0) {
+    s = check_on_device(p, L, stats, st, &max_atoms, &max_tors);
+    if (s != LG_OK) return s;
+  }
   if (O->trace && O->trace_kmax < max_tors) return fail(LG_ERR_INVALID_ARG, "trace_kmax %d < largest bond count %d", O->trace_kmax, max_tors);
 
   lg::DockDev D;
@@ -571,7 +592,7 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
     return e;
   };
 
-  if (!tu.use_graph) {
+  if (!tu.use_graph || direct) {
     std::vector<lg_bucket_stat> launches;
     s = plan(launches);
     if (s != LG_OK) return s;
@@ -613,6 +634,235 @@ lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* 
   p->timed = false;
   LG_HIP(hipGraphLaunch(p->gexec, st));
   return LG_OK;
+}
+
+// Host-side validation of a host-resident library (the device check's rules):
+// offsets from 0, non-decreasing, totals; 1..LG_MAX_ATOMS atoms and
+// 0..LG_MAX_TORSIONS bonds per ligand; bond atoms are local ids in range.
+lg_status check_host_ligands(const lg_host_ligands* H) {
+  if (!H) return fail(LG_ERR_INVALID_ARG, "ligands is NULL");
+  if (H->n < 0 || H->total_atoms < 0 || H->total_torsions < 0) return fail(LG_ERR_INVALID_ARG, "negative sizes");
+  if (!H->atom_offset || !H->tors_offset) return fail(LG_ERR_INVALID_ARG, "offsets are required");
+  if (H->n > 0 && (!H->x || !H->y || !H->z || !H->frag_mask || !H->ref_point))
+    return fail(LG_ERR_INVALID_ARG, "x, y, z, frag_mask and ref_point are required");
+  if (H->total_torsions > 0 && (!H->tors_atoms || !H->inv_bond_len))
+    return fail(LG_ERR_INVALID_ARG, "tors_atoms and inv_bond_len are required");
+  if (H->atom_offset[0] != 0 || H->tors_offset[0] != 0 || H->atom_offset[H->n] != H->total_atoms ||
+      H->tors_offset[H->n] != H->total_torsions)
+    return fail(LG_ERR_INVALID_ARG, "offsets must start at 0 and end at the totals");
+  for (int i = 0; i < H->n; ++i) {
+    const int N = H->atom_offset[i + 1] - H->atom_offset[i], K = H->tors_offset[i + 1] - H->tors_offset[i];
+    if (N < 1 || N > LG_MAX_ATOMS) return fail(LG_ERR_LIMIT, "ligand %d has %d atoms, allowed 1..%d", i, N, LG_MAX_ATOMS);
+    if (K < 0 || K > LG_MAX_TORSIONS) return fail(LG_ERR_LIMIT, "ligand %d has %d bonds, allowed 0..%d", i, K, LG_MAX_TORSIONS);
+    for (int k = H->tors_offset[i]; k < H->tors_offset[i + 1]; ++k)
+      if (H->tors_atoms[2 * k] < 0 || H->tors_atoms[2 * k] >= N || H->tors_atoms[2 * k + 1] < 0 ||
+          H->tors_atoms[2 * k + 1] >= N)
+        return fail(LG_ERR_INVALID_ARG, "ligand %d: bond atom ids out of range", i);
+  }
+  return LG_OK;
+}
+
+extern "C" {
+
+lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* P, const lg_dock_out* O,
+                        void* stream) {
+  return dock_batch_impl(p, L, P, O, stream, -1, -1, false);
+}
+
+lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_params* P, int32_t chunk,
+                         const lg_host_out* O, void* stream) {
+  if (!p || !P || !O) return fail(LG_ERR_INVALID_ARG, "pocket, params and out must not be NULL");
+  lg_status s = check_host_ligands(H);
+  if (s != LG_OK) return s;
+  if (chunk < 1) return fail(LG_ERR_INVALID_ARG, "chunk %d < 1", chunk);
+  if (P->top_k < 1 || P->top_k > P->restarts || P->restarts > LG_MAX_RESTARTS)
+    return fail(LG_ERR_INVALID_ARG, "top_k %d outside 1..R", P->top_k);
+  if (H->n > 0 && (!O->score || !O->restart_id || !O->x || !O->y || !O->z))
+    return fail(LG_ERR_INVALID_ARG, "score, restart_id and x/y/z outputs are required");
+  if (H->n == 0) return LG_OK;
+  const int k = P->top_k;
+  hipStream_t cs = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+
+  // chunks of consecutive ligands; per chunk its largest ligand and bond count
+  struct Chunk { int c0, c1, max_atoms, max_tors; };
+  std::vector<Chunk> chunks;
+  int cap_n = 0, cap_atoms = 0, cap_tors = 0, mx_tors = 0;
+  for (int c0 = 0; c0 < H->n; c0 += chunk) {
+    Chunk c{c0, std::min(H->n, c0 + chunk), 0, 0};
+    for (int i = c.c0; i < c.c1; ++i) {
+      c.max_atoms = std::max(c.max_atoms, H->atom_offset[i + 1] - H->atom_offset[i]);
+      c.max_tors = std::max(c.max_tors, H->tors_offset[i + 1] - H->tors_offset[i]);
+    }
+    cap_n = std::max(cap_n, c.c1 - c.c0);
+    cap_atoms = std::max(cap_atoms, H->atom_offset[c.c1] - H->atom_offset[c.c0]);
+    cap_tors = std::max(cap_tors, H->tors_offset[c.c1] - H->tors_offset[c.c0]);
+    mx_tors = std::max(mx_tors, c.max_tors);
+    chunks.push_back(c);
+  }
+  // the workspace of the largest chunk, allocated before anything is in flight
+  s = ensure_ws(p, dock_ws_layout(cap_n, P->restarts, P->sweeps, cap_tors,
+                                  p->tuning.n_atom_clusters * p->tuning.n_rot_clusters).bytes);
+  if (s != LG_OK) return s;
+
+  // one slot = device inputs + outputs of a chunk and their pinned host staging
+  Layout lay;
+  const size_t o_aoff = lay.take((size_t)(cap_n + 1) * 4), o_toff = lay.take((size_t)(cap_n + 1) * 4);
+  const size_t o_x = lay.take((size_t)cap_atoms * 4), o_y = lay.take((size_t)cap_atoms * 4);
+  const size_t o_z = lay.take((size_t)cap_atoms * 4), o_mask = lay.take((size_t)cap_atoms * 4);
+  const size_t o_tat = lay.take((size_t)2 * cap_tors * 4 + 4), o_il = lay.take((size_t)cap_tors * 4 + 4);
+  const size_t o_ref = lay.take((size_t)3 * cap_n * 4);
+  const size_t in_bytes = lay.off;
+  const size_t o_sc = lay.take((size_t)cap_n * k * 4), o_rid = lay.take((size_t)cap_n * k * 4);
+  const size_t o_piv = lay.take((size_t)3 * cap_n * k * 4);
+  const size_t o_ox = lay.take((size_t)k * cap_atoms * 4), o_oy = lay.take((size_t)k * cap_atoms * 4);
+  const size_t o_oz = lay.take((size_t)k * cap_atoms * 4);
+  const size_t slot_bytes = lay.off;
+  char* dev[2] = {nullptr, nullptr};
+  char* host[2] = {nullptr, nullptr};
+  hipStream_t cin = nullptr, cout = nullptr;
+  hipEvent_t ev_in[2] = {}, ev_dock[2] = {}, ev_out[2] = {};
+  auto release = [&]() {
+    (void)hipStreamSynchronize(cs);
+    for (int i = 0; i < 2; ++i) {
+      if (ev_out[i]) (void)hipEventSynchronize(ev_out[i]);
+    }
+    if (cin) (void)hipStreamSynchronize(cin);
+    if (cout) (void)hipStreamSynchronize(cout);
+    for (int i = 0; i < 2; ++i) {
+      if (dev[i]) (void)hipFree(dev[i]);
+      if (host[i]) (void)hipHostFree(host[i]);
+      for (hipEvent_t e : {ev_in[i], ev_dock[i], ev_out[i]})
+        if (e) (void)hipEventDestroy(e);
+    }
+    if (cin) (void)hipStreamDestroy(cin);
+    if (cout) (void)hipStreamDestroy(cout);
+  };
+  bool ok = true;
+  for (int i = 0; i < 2 && ok; ++i) {
+    ok = hipMalloc((void**)&dev[i], slot_bytes) == hipSuccess &&
+         hipHostMalloc((void**)&host[i], slot_bytes, hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&ev_in[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ev_dock[i], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&ev_out[i], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipStreamCreateWithFlags(&cin, hipStreamNonBlocking) == hipSuccess &&
+       hipStreamCreateWithFlags(&cout, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    release();
+    return fail(LG_ERR_OUT_OF_MEMORY, "stream buffers (2 x %zu bytes device and pinned host) could not be allocated", slot_bytes);
+  }
+
+  // results of chunk c (in slot c % 2, copied back) into the caller's arrays
+  auto unpack = [&](const Chunk& c) {
+    const char* h = host[(&c - chunks.data()) % 2];
+    const size_t nk = (size_t)(c.c1 - c.c0) * k;
+    const size_t a0 = (size_t)H->atom_offset[c.c0], na = (size_t)H->atom_offset[c.c1] - a0;
+    std::memcpy(O->score + (size_t)c.c0 * k, h + o_sc, nk * 4);
+    std::memcpy(O->restart_id + (size_t)c.c0 * k, h + o_rid, nk * 4);
+    if (O->pivot) std::memcpy(O->pivot + (size_t)c.c0 * k * 3, h + o_piv, nk * 12);
+    std::memcpy(O->x + k * a0, h + o_ox, (size_t)k * na * 4);
+    std::memcpy(O->y + k * a0, h + o_oy, (size_t)k * na * 4);
+    std::memcpy(O->z + k * a0, h + o_oz, (size_t)k * na * 4);
+  };
+  auto copy = [&](void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t st) -> hipError_t {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, kind, st) : hipSuccess;
+  };
+
+  const int nc = (int)chunks.size();
+  for (int ci = 0; ci < nc && s == LG_OK; ++ci) {
+    const Chunk& c = chunks[ci];
+    const int sl = ci % 2;
+    char* h = host[sl];
+    char* d = dev[sl];
+    // the slot's previous chunk must be back on the host before its staging is reused
+    if (ci >= 2) {
+      if (hipEventSynchronize(ev_out[sl]) != hipSuccess) { s = fail(LG_ERR_DEVICE, "stream copy-back failed"); break; }
+      unpack(chunks[ci - 2]);
+    }
+    // pack: offsets rebased to the chunk, arrays copied into pinned staging
+    const int n = c.c1 - c.c0;
+    const int a0 = H->atom_offset[c.c0], na = H->atom_offset[c.c1] - a0;
+    const int t0 = H->tors_offset[c.c0], nt = H->tors_offset[c.c1] - t0;
+    int32_t* ao = (int32_t*)(h + o_aoff);
+    int32_t* to = (int32_t*)(h + o_toff);
+    for (int i = 0; i <= n; ++i) {
+      ao[i] = H->atom_offset[c.c0 + i] - a0;
+      to[i] = H->tors_offset[c.c0 + i] - t0;
+    }
+    std::memcpy(h + o_x, H->x + a0, (size_t)na * 4);
+    std::memcpy(h + o_y, H->y + a0, (size_t)na * 4);
+    std::memcpy(h + o_z, H->z + a0, (size_t)na * 4);
+    std::memcpy(h + o_mask, H->frag_mask + a0, (size_t)na * 4);
+    if (nt > 0) {
+      std::memcpy(h + o_tat, H->tors_atoms + 2 * (size_t)t0, (size_t)nt * 8);
+      std::memcpy(h + o_il, H->inv_bond_len + t0, (size_t)nt * 4);
+    }
+    std::memcpy(h + o_ref, H->ref_point + 3 * (size_t)c.c0, (size_t)n * 12);
+    // copy in once the slot's previous docking no longer reads its inputs
+    hipError_t e = hipSuccess;
+    if (ci >= 2) e = hipStreamWaitEvent(cin, ev_dock[sl], 0);
+    for (size_t off : {o_aoff, o_toff})
+      if (e == hipSuccess) e = copy(d + off, h + off, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, cin);
+    for (size_t off : {o_x, o_y, o_z, o_mask})
+      if (e == hipSuccess) e = copy(d + off, h + off, (size_t)na * 4, hipMemcpyHostToDevice, cin);
+    if (e == hipSuccess) e = copy(d + o_tat, h + o_tat, (size_t)nt * 8, hipMemcpyHostToDevice, cin);
+    if (e == hipSuccess) e = copy(d + o_il, h + o_il, (size_t)nt * 4, hipMemcpyHostToDevice, cin);
+    if (e == hipSuccess) e = copy(d + o_ref, h + o_ref, (size_t)n * 12, hipMemcpyHostToDevice, cin);
+    if (e == hipSuccess) e = hipEventRecord(ev_in[sl], cin);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev_in[sl], 0);
+    if (e != hipSuccess) { s = fail(LG_ERR_DEVICE, "stream copy-in failed: %s", hipGetErrorString(e)); break; }
+    // dock the chunk on the caller's stream
+    lg_ligands L;
+    L.n = n;
+    L.total_atoms = na;
+    L.total_torsions = nt;
+    L.atom_offset = (const int32_t*)(d + o_aoff);
+    L.tors_offset = (const int32_t*)(d + o_toff);
+    L.x = (const float*)(d + o_x);
+    L.y = (const float*)(d + o_y);
+    L.z = (const float*)(d + o_z);
+    L.frag_mask = (const uint32_t*)(d + o_mask);
+    L.tors_atoms = (const int32_t*)(d + o_tat);
+    L.inv_bond_len = (const float*)(d + o_il);
+    L.ref_point = (const float*)(d + o_ref);
+    L.atom_offset_host = ao;
+    L.tors_offset_host = to;
+    lg_dock_out DO;
+    std::memset(&DO, 0, sizeof DO);
+    DO.score = (float*)(d + o_sc);
+    DO.restart_id = (int32_t*)(d + o_rid);
+    DO.pivot = (float*)(d + o_piv);
+    DO.x = (float*)(d + o_ox);
+    DO.y = (float*)(d + o_oy);
+    DO.z = (float*)(d + o_oz);
+    lg_dock_params DP = *P;
+    DP.mode = LG_BUCKETED;
+    s = dock_batch_impl(p, &L, &DP, &DO, cs, c.max_atoms, c.max_tors, true);
+    if (s != LG_OK) break;
+    e = hipEventRecord(ev_dock[sl], cs);
+    // copy the results out behind the docking
+    if (e == hipSuccess) e = hipStreamWaitEvent(cout, ev_dock[sl], 0);
+    const size_t nk = (size_t)n * k;
+    for (size_t off : {o_sc, o_rid})
+      if (e == hipSuccess) e = copy(h + off, d + off, nk * 4, hipMemcpyDeviceToHost, cout);
+    if (e == hipSuccess && O->pivot) e = copy(h + o_piv, d + o_piv, nk * 12, hipMemcpyDeviceToHost, cout);
+    for (size_t off : {o_ox, o_oy, o_oz})
+      if (e == hipSuccess) e = copy(h + off, d + off, (size_t)k * na * 4, hipMemcpyDeviceToHost, cout);
+    if (e == hipSuccess) e = hipEventRecord(ev_out[sl], cout);
+    if (e != hipSuccess) { s = fail(LG_ERR_DEVICE, "stream copy-out failed: %s", hipGetErrorString(e)); break; }
+  }
+  // the last two chunks
+  for (int ci = std::max(0, nc - 2); ci < nc && s == LG_OK; ++ci) {
+    if (hipEventSynchronize(ev_out[ci % 2]) != hipSuccess) {
+      s = fail(LG_ERR_DEVICE, "stream copy-back failed");
+      break;
+    }
+    unpack(chunks[ci]);
+  }
+  release();
+  return s;
 }
 
 int32_t lg_bucket_stats(lg_pocket p, lg_bucket_stat* out, int32_t capacity) {

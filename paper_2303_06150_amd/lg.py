@@ -25,7 +25,8 @@ LG_NEAREST, LG_TRILINEAR = 0, 1
 LG_PLAIN, LG_BUCKETED = 0, 1
 LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
 
-EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_rank", "lg_autotune",
+EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_stream", "lg_score", "lg_refine", "lg_rank",
+           "lg_autotune",
            "lg_set_tuning", "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
            "lg_last_error", "lg_version")
 
@@ -65,6 +66,18 @@ class lg_dock_out(ctypes.Structure):
                 ("pivot", c_void_p)]
 
 
+class lg_host_ligands(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("total_atoms", c_int32), ("total_torsions", c_int32),
+                ("atom_offset", c_void_p), ("tors_offset", c_void_p), ("x", c_void_p), ("y", c_void_p),
+                ("z", c_void_p), ("frag_mask", c_void_p), ("tors_atoms", c_void_p),
+                ("inv_bond_len", c_void_p), ("ref_point", c_void_p)]
+
+
+class lg_host_out(ctypes.Structure):
+    _fields_ = [("score", c_void_p), ("restart_id", c_void_p), ("x", c_void_p), ("y", c_void_p),
+                ("z", c_void_p), ("pivot", c_void_p)]
+
+
 class lg_refine_params(ctypes.Structure):
     _fields_ = [("steps", c_int32), ("eta_t", c_float), ("eta_w", c_float), ("eta_th", c_float),
                 ("clip_t", c_float), ("clip_w", c_float), ("clip_th", c_float), ("clash_dist2", c_float),
@@ -101,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.lg_load_pocket.argtypes = [P(lg_pocket_desc), c_void_p, c_int32, c_void_p, P(c_void_p)]
     lib.lg_free_pocket.argtypes = [c_void_p]
     lib.lg_dock_batch.argtypes = [c_void_p, P(lg_ligands), P(lg_dock_params), P(lg_dock_out), c_void_p]
+    lib.lg_dock_stream.argtypes = [c_void_p, P(lg_host_ligands), P(lg_dock_params), c_int32, P(lg_host_out),
+                                   c_void_p]
     lib.lg_score.argtypes = [c_void_p, P(lg_ligands), c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                              c_void_p, c_void_p]
     lib.lg_refine.argtypes = [c_void_p, P(lg_ligands), P(lg_refine_params), c_void_p, c_void_p, c_void_p,
@@ -117,7 +132,7 @@ def load_library(path: str = LIB_PATH):
     lib.lg_atom_clusters.argtypes = [c_int32, c_int32, c_int32, P(c_int32)]
     lib.lg_rotamer_clusters.argtypes = [c_int32, c_int32, P(c_int32)]
     lib.lg_last_error.restype = ctypes.c_char_p
-    for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_score", "lg_refine", "lg_rank",
+    for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_stream", "lg_score", "lg_refine", "lg_rank",
                  "lg_autotune", "lg_set_tuning", "lg_get_tuning"):
         getattr(lib, name).restype = c_int32
     _lib = lib
@@ -297,6 +312,36 @@ def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_tabl
     L = ligs.struct()
     _check(_lib.lg_dock_batch(pocket.handle, ctypes.byref(L), ctypes.byref(params), ctypes.byref(o),
                               _stream_handle(stream)))
+    return out
+
+
+def lg_dock_stream(pocket: Pocket, atom_offset, tors_offset, x, y, z, frag_mask, tors_atoms, inv_bond_len,
+                   ref_point, restart_table, angle_table, *, sweeps: int, top_k: int, trans_samples: int,
+                   trans_step: float, clash_dist2: float, chunk: int, want_pivot: bool = True, stream=None):
+    """Dock a library held in host memory (numpy arrays), streamed through the
+    device in chunks.  Returns numpy arrays: score [n,k], restart_id [n,k],
+    x/y/z [k*total_atoms], pivot [n,k,3] (if asked)."""
+    arrs = [np.ascontiguousarray(atom_offset, np.int32), np.ascontiguousarray(tors_offset, np.int32),
+            np.ascontiguousarray(x, np.float32), np.ascontiguousarray(y, np.float32),
+            np.ascontiguousarray(z, np.float32), np.ascontiguousarray(frag_mask, np.uint32),
+            np.ascontiguousarray(tors_atoms, np.int32).reshape(-1), np.ascontiguousarray(inv_bond_len, np.float32),
+            np.ascontiguousarray(ref_point, np.float32).reshape(-1)]
+    n = len(arrs[0]) - 1
+    ta, tt = int(arrs[0][-1]), int(arrs[1][-1])
+    ptr = [a.ctypes.data_as(c_void_p) for a in arrs]
+    H = lg_host_ligands(n, ta, tt, *ptr)
+    R, A = int(restart_table.shape[0]), int(angle_table.shape[0])
+    params = lg_dock_params(R, A, int(trans_samples), int(sweeps), int(top_k), LG_BUCKETED, float(trans_step),
+                            float(clash_dist2), _ptr(restart_table), _ptr(angle_table))
+    out = dict(score=np.empty((n, top_k), np.float32), restart_id=np.empty((n, top_k), np.int32),
+               x=np.empty(top_k * ta, np.float32), y=np.empty(top_k * ta, np.float32),
+               z=np.empty(top_k * ta, np.float32))
+    if want_pivot:
+        out["pivot"] = np.empty((n, top_k, 3), np.float32)
+    O = lg_host_out(*[out[k_].ctypes.data_as(c_void_p) if k_ in out else None
+                      for k_ in ("score", "restart_id", "x", "y", "z", "pivot")])
+    _check(_lib.lg_dock_stream(pocket.handle, ctypes.byref(H), ctypes.byref(params), int(chunk), ctypes.byref(O),
+                               _stream_handle(stream)))
     return out
 
 

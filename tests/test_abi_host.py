@@ -63,6 +63,7 @@ def test_argument_checks_need_no_device():
     assert lib.lg_refine(None, None, None, None, None, None, None, None) != lg.LG_OK
     assert lib.lg_rank(None, None, 0, 1, 0, None, None, None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_autotune(None, None, None, 1, None, None, None) == lg.LG_ERR_INVALID_ARG
+    assert lib.lg_dock_stream(None, None, None, 1, None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_set_tuning(None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_free_pocket(None) == lg.LG_OK
     desc = lg.lg_pocket_desc(1, 32, 32, 0.5, 2.0, (ctypes.c_float * 3)(), (ctypes.c_float * 3)(), 0.0)

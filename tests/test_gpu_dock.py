@@ -340,3 +340,39 @@ def test_autotune_keeps_results(lgmod):
         f"waves/block {list(t.waves_per_block)}, lazy clash {t.lazy_clash}, "
         f"{t.n_atom_clusters} x {t.n_rot_clusters} clusters")
     pocket.free()
+
+
+def test_degenerate_cases(lgmod, tiny):
+    """An empty batch through every call; A = T = 1 (only the identity sample)
+    and S = 0 (no sweeps): the kept poses are the placements, bitwise as in the
+    oracle."""
+    lg = lgmod
+    import torch
+    w, pk, L = tiny["w"], tiny["pocket"], tiny["ligs"]
+    pocket = device_pocket(pk)
+    empty = L.subset(np.array([], np.int64))
+    de = lg.device_ligands(empty.atom_offset, empty.tors_offset, empty.x, empty.y, empty.z, empty.frag_mask,
+                           empty.tors_atoms, empty.inv_bond_len, empty.ref_point)
+    rt = torch.from_numpy(tiny["r32"]).cuda()
+    at = torch.from_numpy(tiny["a32"]).cuda()
+    out = lg.lg_dock_batch(pocket, de, rt, at, sweeps=1, top_k=2, trans_samples=64, trans_step=0.0625,
+                           clash_dist2=oracle.CLASH2)
+    assert out["score"].numel() == 0 and out["x"].numel() == 0
+    assert lg.lg_refine(pocket, de, lg.refine_params())["score"].numel() == 0
+    assert lg.lg_score(pocket, de, lg.LG_TRILINEAR, grad=True)["score"].numel() == 0
+    assert lg.lg_rank(pocket, torch.empty(0, device="cuda"), 4, 0)["top_idx"].numel() == 0
+
+    sub = L.subset(np.arange(6))
+    one = np.array([[1.0, 0.0]], np.float32)
+    for A, S in ((1, 2), (64, 0)):
+        a32 = one if A == 1 else tiny["a32"]
+        say(f"degenerate: A = T = {A}, S = {S}")
+        got = dock_gpu(pocket, sub, tiny["r32"], a32, T=A, S=S, top_k=4, mode=lg.LG_BUCKETED, trace=S > 0)
+        for i in range(sub.n):
+            ref = dock_oracle(pk, sub, i, tiny["r32"], a32, T=A, S=S)
+            compare_ligand(got, sub, i, ref, np.arange(w.restarts), 4, w.restarts, f"A={A} S={S}")
+            for r in range(w.restarts):
+                start, P0 = oracle.place(sub.ligand(i), tiny["r32"][r].astype(np.float64),
+                                         pk.center.astype(np.float64), bits=32)
+                np.testing.assert_array_equal(ref["poses"][r], start)
+    pocket.free()
