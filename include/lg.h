@@ -4,12 +4,14 @@
  * The calls follow the paper's statement of the virtual-screening problem
  * (Sec. 2): identify a docking site (lg_load_pocket), dock every ligand of a
  * bucket into it, i.e. estimate the 3D placement of its atoms
- * (lg_dock_batch), evaluate the interaction strength and rank the library
- * (lg_score), and refine the best poses locally (lg_refine).  Buckets of
- * ligands of similar atom and rotamer counts, each docked by a kernel
- * instantiated for its size class with a bucket size derived from occupancy,
- * are the paper's out-of-kernel optimisation (Sec. 3, Eq. 1); lg_dock_batch
- * with LG_BUCKETED is its GPU-side form.
+ * (lg_dock_batch; lg_dock_stream for a library held in host memory),
+ * evaluate the interaction strength (lg_score), refine the best poses locally
+ * (lg_refine) and rank the library (lg_rank).  Buckets of ligands of similar
+ * atom and rotamer counts, each docked by a kernel instantiated for its size
+ * class with a bucket size derived from occupancy, are the paper's
+ * out-of-kernel optimisation (Sec. 3, Eq. 1); lg_dock_batch with LG_BUCKETED is
+ * its GPU-side form, and lg_autotune picks its buckets and kernel shapes by
+ * measurement.
  *
  * Conventions (all entry points):
  *  - Pointers marked "device" are device memory; "host" are host memory.
@@ -18,7 +20,8 @@
  *    asynchronous: keep buffers alive until the stream has completed.
  *  - Every call returns an lg_status; nothing throws across the ABI and
  *    nothing aborts.  Argument and limit checks are synchronous and return
- *    before any work is enqueued.  HIP errors map to LG_ERR_DEVICE and are
+ *    before any work is enqueued (device-resident ligand data is checked by a
+ *    small kernel whose counters are read back before the docking work).  HIP errors map to LG_ERR_DEVICE and are
  *    reported by the call that observes them.  lg_last_error() gives a
  *    message for the last failing call of the calling thread.
  *  - Coordinates are Angstrom, FP32.  Arithmetic is FP32 with explicit fma
@@ -292,7 +295,7 @@ lg_status lg_get_tuning(lg_pocket pocket, lg_tuning* tuning);
 /* Autotuner of the bucketed path (the input-aware choices of Sec. 3 -- size
  * buckets and kernel shapes -- searched by measurement on the device).  Docks
  * the sample `ligands` with `params` (mode ignored: bucketed) repeatedly under
- * candidate tunings and keeps, by coordinate descent over `passes` rounds, any
+ * candidate tunings and keeps, by coordinate descent over `passes` passes, any
  * candidate at least 1 % faster: size buckets (one per kernel instance, with
  * or without rotamer clusters, or a single bucket), wavefronts per block of
  * each instance in use, restart chunk, persistent grid scale and the clash
