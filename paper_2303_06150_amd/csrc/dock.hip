@@ -37,6 +37,8 @@ template <int SPL>
 struct SampleReg {
   float c[SPL], s[SPL], d[SPL];
   uint32_t valid_a, valid_t;   // bit q: sample lane + 64 q exists
+  bool half_turn;              // A = 64 SPL and sample j + A/2 is sample j turned by pi:
+                               // (cos, sin) of the two are exact negatives
 };
 
 
@@ -207,7 +209,28 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
       out[q] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
     }
   };
-  pipelined_sum<SPL>(N, gather, acc);
+  // samples j and j + A/2: with (cos, sin) negated the rotated offsets are the
+  // exact negatives (fma and products are sign-symmetric), so one 2-D rotation
+  // serves both; a zero's sign cannot change the node
+  auto gather_half_turn = [&](int t, float (&out)[SPL]) {
+    const float4 d = scr[t];
+    const int part = __float_as_int(d.z);
+#pragma unroll
+    for (int q = 0; q < SPL / 2; ++q) {
+      float np = fmaf(sm.c[q], d.x, -(sm.s[q] * d.y));
+      float nq = fmaf(sm.s[q], d.x, sm.c[q] * d.y);
+      int ip = clamp_node(fmaf(pP + np, ih, cP), fnP);
+      int iq = clamp_node(fmaf(pQ + nq, ih, cQ), fnQ);
+      out[q] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+      ip = clamp_node(fmaf(pP - np, ih, cP), fnP);
+      iq = clamp_node(fmaf(pQ - nq, ih, cQ), fnQ);
+      out[q + SPL / 2] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+    }
+  };
+  if (SPL % 2 == 0 && sm.half_turn)
+    pipelined_sum<SPL>(N, gather_half_turn, acc);
+  else
+    pipelined_sum<SPL>(N, gather, acc);
   if (lane == 0) acc[0] = s0;   // sample 0 is the current pose
   const int j = wave_argmax(acc, sm.valid_a);
   apply_rot<NSLOT, E>(D, p, j);
@@ -420,6 +443,7 @@ __device__ void load_samples(const DockDev& D, SampleReg<SPL>& sm) {
   const int lane = lane_id();
   sm.valid_a = 0u;
   sm.valid_t = 0u;
+  sm.half_turn = false;
 #pragma unroll
   for (int q = 0; q < SPL; ++q) {
     const int j = lane + 64 * q;
@@ -438,6 +462,13 @@ __device__ void load_samples(const DockDev& D, SampleReg<SPL>& sm) {
     } else {
       sm.d[q] = 0.f;
     }
+  }
+  if (SPL % 2 == 0 && D.A == 64 * SPL) {
+    bool pair = true;
+#pragma unroll
+    for (int q = 0; q < SPL / 2; ++q)
+      pair = pair && sm.c[q + SPL / 2] == -sm.c[q] && sm.s[q + SPL / 2] == -sm.s[q];
+    sm.half_turn = !wave_any(!pair);
   }
 }
 
