@@ -107,6 +107,85 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+def replicate(L, count):
+    """count copies of the single ligand of L, as one batch (host arrays)."""
+    N, K = int(L.n_atoms[0]), int(L.n_tors[0])
+    ao = np.arange(count + 1, dtype=np.int32) * N
+    to = np.arange(count + 1, dtype=np.int32) * K
+    tile = lambda a, r=1: np.tile(np.asarray(a), count)
+    return (ao, to, tile(L.x), tile(L.y), tile(L.z), tile(L.frag_mask), tile(L.tors_atoms),
+            tile(L.inv_bond_len), tile(L.ref_point))
+
+
+def experiment_bucket_size(lg, torch, pocket, rt, at, kw, log):
+    """The bucket-size experiment of Sec. 5 (Fig. 2) on synthetic replicas: one
+    ligand of 17, 53 or 99 atoms replicated, docked in batches of l ligands;
+    throughput against l.  l_fill = resident wavefronts x restart chunk / R is the
+    batch that fills the chip once (one wavefront per work item of chunk restarts),
+    the MI355X form of Eq. 1 for this mapping."""
+    import gen
+    t = pocket.get_tuning()
+    rows = []
+    for N in (17, 53, 99):
+        K = int(round(0.18 * N))
+        L1 = gen.ligands_from_sizes(np.array([9_000_000 + N]), 0, np.array([N]), np.array([K]))
+        probe = lg.device_ligands(*replicate(L1, 64))
+        lg.lg_dock_batch(pocket, probe, rt, at, mode=lg.LG_BUCKETED, **kw)
+        torch.cuda.synchronize()
+        st = pocket.bucket_stats()
+        waves = max(b["blocks"] * b["waves_per_block"] for b in st)
+        R = int(rt.shape[0])
+        l_fill = max(1, waves * t.restart_chunk // R)
+        for m in (1, 2, 3, 4, 5, 6, 9, 12, 24):
+            l = max(1, l_fill * m // 3)
+            dl = lg.device_ligands(*replicate(L1, l))
+            out = lg.lg_dock_batch(pocket, dl, rt, at, mode=lg.LG_BUCKETED, **kw)
+            torch.cuda.synchronize()
+            reps = max(1, -(-max(2000, 4 * l) // l))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = lg.lg_dock_batch(pocket, dl, rt, at, mode=lg.LG_BUCKETED, out=out, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows.append(dict(atoms=N, bonds=K, l_fill=l_fill, ligands_per_batch=l, thirds_of_fill=m,
+                             value=round(l * reps / dt, 1), unit="ligands/s"))
+            log(f"bucket size: {N} atoms, l = {l} ({m}/3 of {l_fill}): {l * reps / dt:.1f} ligands/s")
+    return dict(experiment="bucket_size", restart_chunk=t.restart_chunk, rows=rows)
+
+
+def experiment_clusters(lg, torch, pocket, dl, rt, at, kw, n, log):
+    """The cluster experiment of Sec. 5 (Fig. 4): throughput of the mixed library
+    for atom clusters x rotamer clusters, against one cluster of each."""
+    base = pocket.get_tuning()
+    rows = []
+    for na_bounds in ([256], [64, 256], [64, 128, 192, 256]):
+        for nr in (1, 2, 4, 8, 23):
+            t = lg.lg_tuning.from_buffer_copy(base)
+            t.n_atom_clusters = len(na_bounds)
+            for c, b in enumerate(na_bounds):
+                t.atom_bounds[c] = b
+            rb = lg.lg_rotamer_clusters(nr, 24)
+            t.n_rot_clusters = len(rb)
+            for c, b in enumerate(rb):
+                t.rot_bounds[c] = b
+            pocket.set_tuning(t)
+            out = lg.lg_dock_batch(pocket, dl, rt, at, mode=lg.LG_BUCKETED, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                out = lg.lg_dock_batch(pocket, dl, rt, at, mode=lg.LG_BUCKETED, out=out, **kw)
+            torch.cuda.synchronize()
+            v = 2 * n / (time.perf_counter() - t0)
+            rows.append(dict(atom_clusters=len(na_bounds), rotamer_clusters=len(rb), value=round(v, 1),
+                             unit="ligands/s"))
+            log(f"clusters: {len(na_bounds)} x {len(rb)}: {v:.1f} ligands/s")
+    pocket.set_tuning(base)
+    one = rows[0]["value"]
+    for r in rows:
+        r["speedup_vs_one_cluster"] = round(r["value"] / one, 3)
+    return dict(experiment="clusters", ligands=n, rows=rows)
+
+
 def cpu_baseline(w, sample_ids, procs):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import multiprocessing as mp
@@ -156,6 +235,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side-runs", action="store_true", help="skip the plain and ablation runs")
+    ap.add_argument("--experiment", choices=("bucket-size", "clusters"), default=None,
+                    help="run one of the paper's experiments on synthetic inputs instead of the benchmark "
+                         "(prints its own JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -197,6 +279,15 @@ def main():
 
     def dock(ligs, mode, out=None):
         return lg.lg_dock_batch(pocket, ligs, rt, at, mode=mode, out=out, **kw)
+
+    if args.experiment == "bucket-size":
+        print(json.dumps(experiment_bucket_size(lg, torch, pocket, rt, at, kw, log)), flush=True)
+        pocket.free()
+        return
+    if args.experiment == "clusters":
+        print(json.dumps(experiment_clusters(lg, torch, pocket, dl, rt, at, kw, n, log)), flush=True)
+        pocket.free()
+        return
 
     # ---- autotuning on a prefix of the library (reported, not timed)
     tune = None
