@@ -1123,21 +1123,54 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
   if (L->n == 0) return LG_OK;
   hipStream_t st = (hipStream_t)stream;
   LG_HIP(hipSetDevice(p->device));
+  const int n = L->n;
+  lg::ClusterBounds cb;
+  std::memset(&cb, 0, sizeof cb);
+  cb.na = LG_MAX_ATOMS / 64;   // one size class per kernel instance (atom slots)
+  for (int c = 0; c < cb.na; ++c) cb.atom[c] = 64 * (c + 1);
+  cb.nr = 1;
+  cb.rot[0] = LG_MAX_TORSIONS;
   Layout lay;
   const size_t o_stats = lay.take(16 * sizeof(int32_t));
+  const size_t o_cls = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_perm = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_cnt = lay.take((size_t)(4 * cb.na + 1) * sizeof(int32_t));
   s = ensure_ws(p, lay.off);
   if (s != LG_OK) return s;
+  char* ws = (char*)p->ws;
   int max_atoms = 0, max_tors = 0;
-  s = check_on_device(p, L, (int32_t*)((char*)p->ws + o_stats), st, &max_atoms, &max_tors);
+  s = check_on_device(p, L, (int32_t*)(ws + o_stats), st, &max_atoms, &max_tors);
   if (s != LG_OK) return s;
   lg::RefineDev R;
+  R.lig_ids = nullptr;
   R.steps = rp->steps;
   R.kpl = rp->poses_per_ligand;
   R.eta_t = rp->eta_t; R.eta_w = rp->eta_w; R.eta_th = rp->eta_th;
   R.clip_t = rp->clip_t; R.clip_w = rp->clip_w; R.clip_th = rp->clip_th;
   R.clash2 = rp->clash_dist2;
   R.xo = x_out; R.yo = y_out; R.zo = z_out; R.score = score_out;
-  LG_HIP(lg::launch_refine((max_atoms + 63) / 64, p->grid, lig_dev(L), R, L->n * rp->poses_per_ligand, st));
+  const int kpl = rp->poses_per_ligand;
+  if (max_atoms <= 64) {
+    LG_HIP(lg::launch_refine(1, p->grid, lig_dev(L), R, n * kpl, st));
+    return LG_OK;
+  }
+  // ligands grouped by size class, each class refined by the instance that fits it
+  int32_t* cls = (int32_t*)(ws + o_cls);
+  int32_t* perm = (int32_t*)(ws + o_perm);
+  int32_t* counts = (int32_t*)(ws + o_cnt);
+  int32_t* start = counts + cb.na;
+  int32_t* fill = start + cb.na + 1;
+  int32_t* cursors = fill + cb.na;
+  LG_HIP(lg::launch_bucketing(L->atom_offset, L->tors_offset, n, cb, cls, counts, start, fill, perm, cursors, st));
+  int32_t hs[LG_MAX_ATOMS / 64 + 1];
+  LG_HIP(hipMemcpyAsync(hs, start, sizeof hs, hipMemcpyDeviceToHost, st));
+  LG_HIP(hipStreamSynchronize(st));
+  for (int c = 0; c < cb.na; ++c) {
+    const int cnt = hs[c + 1] - hs[c];
+    if (cnt <= 0) continue;
+    R.lig_ids = perm + hs[c];
+    LG_HIP(lg::launch_refine(c + 1, p->grid, lig_dev(L), R, cnt * kpl, st));
+  }
   return LG_OK;
 }
 

@@ -66,6 +66,7 @@ struct DockDev {
 // i % kpl of ligand i / kpl, its coordinates at kpl*atom_offset[lig] + member*N.
 struct RefineDev {
   int steps, kpl;
+  const int32_t* lig_ids;  // ligands of this launch (a size class), or nullptr: 0..n-1
   float eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash2;
   float* xo;
   float* yo;

@@ -215,9 +215,11 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   float* th = inv_len + 32;                                   // 32 bond gradients / steps (8 float4)
   float* tile = th + 32;                                      // column sums of the gradient
   float* res = tile + TILE_FLOATS;
-  const int i = blockIdx.x * nwaves + wave;   // pose: member i % kpl of ligand i / kpl
-  if (i >= n) return;
-  const int lig = i / Rp.kpl, member = i - lig * Rp.kpl;
+  const int w = blockIdx.x * nwaves + wave;   // pose: member w % kpl of the launch's ligand w / kpl
+  if (w >= n) return;
+  const int li = w / Rp.kpl, member = w - li * Rp.kpl;
+  const int lig = Rp.lig_ids ? __builtin_amdgcn_readfirstlane(Rp.lig_ids[li]) : li;
+  const int i = lig * Rp.kpl + member;        // pose index in the caller's layout
   const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[lig]);
   const int N = __builtin_amdgcn_readfirstlane(P.atom_offset[lig + 1]) - abase;
   const int toff = __builtin_amdgcn_readfirstlane(P.tors_offset[lig]);
