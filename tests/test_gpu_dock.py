@@ -376,3 +376,73 @@ def test_degenerate_cases(lgmod, tiny):
                                          pk.center.astype(np.float64), bits=32)
                 np.testing.assert_array_equal(ref["poses"][r], start)
     pocket.free()
+
+
+def test_bench_configuration_full_library(lgmod):
+    """The benchmark's own configuration: the whole 100k mixed library, buckets
+    chosen by the autotuner, docked through the graph replay.  Sampled restarts
+    and one ligand's full top-10 against the oracle; at full size, properties
+    that hold for every ligand: top-k sorted (equal scores: lower restart),
+    kept scores equal to those restarts' final scores, every kept pose keeps
+    its bond lengths and its rigid root piece about the pivot."""
+    lg = lgmod
+    import torch
+    w = gen.WORKLOADS["mixed"]
+    L = gen.workload_ligands(w)
+    pk = gen.workload_pocket(w)
+    r32, _ = gen.restarts(w.restarts, w.seed)
+    a32, _ = gen.angles(w.angle_samples)
+    pocket = device_pocket(pk)
+    rt, at = torch.from_numpy(r32).cuda(), torch.from_numpy(a32).cuda()
+    T = w.angle_samples
+    kw = dict(sweeps=w.sweeps, top_k=w.top_k, trans_samples=T, trans_step=oracle.trans_step(T),
+              clash_dist2=oracle.CLASH2)
+    sub = L.subset(np.arange(4000))
+    lg.lg_autotune(pocket, lg.device_ligands(sub.atom_offset, sub.tors_offset, sub.x, sub.y, sub.z, sub.frag_mask,
+                                             sub.tors_atoms, sub.inv_bond_len, sub.ref_point), rt, at, **kw)
+    t = pocket.get_tuning()
+    say(f"bench configuration: {L.n} ligands, tuned atom bounds {list(t.atom_bounds[:t.n_atom_clusters])}")
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                           L.inv_bond_len, L.ref_point)
+    out = lg.lg_dock_batch(pocket, dl, rt, at, want_all_scores=True, **kw)
+    out = lg.lg_dock_batch(pocket, dl, rt, at, want_all_scores=True, out=out, **kw)   # graph replay
+    torch.cuda.synchronize()
+    h = {key: v.cpu().numpy() for key, v in out.items()}
+    pocket.free()
+    k = w.top_k
+    # properties over the whole library
+    sc, rid, alls = h["score"], h["restart_id"], h["all_scores"]
+    assert np.all(np.isfinite(alls))
+    assert np.all((sc[:, :-1] > sc[:, 1:]) | ((sc[:, :-1] == sc[:, 1:]) & (rid[:, :-1] < rid[:, 1:])))
+    np.testing.assert_array_equal(np.take_along_axis(alls, rid.astype(np.int64), 1), sc)
+    assert np.all(sc[:, 0] == alls.max(1))
+    N = L.n_atoms.astype(np.int64)
+    base = k * L.atom_offset[:-1].astype(np.int64)
+    lig_of_atom = np.repeat(np.arange(L.n), N)
+    local = np.arange(L.atom_offset[-1]) - L.atom_offset[:-1][lig_of_atom]
+    for q in (0, k - 1):
+        idx = base[lig_of_atom] + q * N[lig_of_atom] + local
+        xyz = np.stack([h["x"][idx], h["y"][idx], h["z"][idx]], 1).astype(np.float64)
+        has_parent = L.parent >= 0
+        child = np.nonzero(has_parent)[0]
+        par = L.atom_offset[:-1][lig_of_atom[child]] + L.parent[child]
+        blen = np.linalg.norm(xyz[child] - xyz[par], axis=1)
+        # FP32 rigid moves keep lengths to ~1e-5 A; a corrupted pose is off by far more
+        assert np.max(np.abs(blen - 1.5)) < 2e-3, f"rank {q}: bond lengths off by {np.max(np.abs(blen - 1.5))}"
+        root = L.frag_mask == 0
+        piv = h["pivot"][lig_of_atom, q].astype(np.float64)
+        d_now = np.linalg.norm(xyz - piv, axis=1)
+        ref_piv = L.ref_point.reshape(-1, 3)[lig_of_atom].astype(np.float64)
+        x0 = np.stack([L.x, L.y, L.z], 1).astype(np.float64)
+        d0 = np.linalg.norm(x0 - ref_piv, axis=1)
+        assert np.max(np.abs(d_now[root] - d0[root])) < 2e-3
+    say("bench configuration: properties hold for every ligand")
+    # sampled restarts and one full ligand against the oracle
+    rng = np.random.default_rng(3)
+    for i in rng.choice(L.n, 8, replace=False):
+        rows = np.sort(rng.choice(w.restarts, 3, replace=False))
+        ref = dock_oracle(pk, L, int(i), r32, a32, T=T, S=w.sweeps, rows=rows)
+        compare_ligand(h, L, int(i), ref, rows, k, w.restarts, "bench configuration")
+    i = int(rng.integers(L.n))
+    ref = dock_oracle(pk, L, i, r32, a32, T=T, S=w.sweeps)
+    compare_ligand(h, L, i, ref, np.arange(w.restarts), k, w.restarts, "bench configuration, all restarts")
