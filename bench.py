@@ -43,6 +43,31 @@ OPS_PLACE = 15    # per atom per restart: placement
 OPS_TRI = 45      # per atom per restart: trilinear final score
 
 
+# Refinement, per pose and step (the op script of one step): per atom the trilinear
+# value with gradient, its score / force / torque sums, the rigid part of the move
+# and the trilinear value after the move; per (bond, moving atom) the bond torque
+# and the torsion move; per bond its axis, step, matrix and step polynomial; per
+# atom pair whose rigid pieces differ the clash test.
+OPS_REF_ATOM = 63 + 19 + 18 + 46
+OPS_REF_BOND_ATOM = 15 + 15
+OPS_REF_BOND = 45
+OPS_REF_PAIR = 7
+
+
+def refine_ops_per_step(L):
+    """Lane-ops of one refinement step of one pose, per ligand of L."""
+    ops = np.zeros(L.n)
+    for i in range(L.n):
+        a0, a1 = L.atom_offset[i], L.atom_offset[i + 1]
+        m = L.frag_mask[a0:a1]
+        N, K = a1 - a0, int(L.n_tors[i])
+        moving = sum(int(((m >> k) & 1).sum()) for k in range(K))
+        _, cnt = np.unique(m, return_counts=True)
+        pairs = N * (N - 1) // 2 - int((cnt * (cnt - 1) // 2).sum())
+        ops[i] = N * OPS_REF_ATOM + moving * OPS_REF_BOND_ATOM + K * OPS_REF_BOND + pairs * OPS_REF_PAIR
+    return ops
+
+
 def algorithmic_ops(n_atoms, frag_sizes_per_lig, R, A, T, S):
     """Lane-ops of docking each ligand (array over ligands).
 
@@ -453,10 +478,37 @@ def main():
             torch.cuda.synchronize()
             rms = e0.elapsed_time(e1)
             gain = (rf["score"].reshape(nrf, kp) - od["score"]).double()
+            rops = float(refine_ops_per_step(Lr).sum()) * kp * args.refine_steps
+            rach = rops / (rms * 1e-3)
             side["refine"] = dict(ligands=nrf, poses=nrf * kp, steps=args.refine_steps, ms=round(rms, 3),
                                   value=round(nrf * kp / (rms * 1e-3), 1), unit="poses/s",
                                   mean_score_gain=round(float(gain.mean()), 4),
-                                  rank_top_m=min(1000, nrf), rank_ms=round(e1.elapsed_time(e2), 3))
+                                  rank_top_m=min(1000, nrf), rank_ms=round(e1.elapsed_time(e2), 3),
+                                  roofline=dict(bound="alu", achieved=round(rach / 1e12, 3),
+                                                peak=round(PEAK_LANE_OPS / 1e12, 3), unit="TOP/s",
+                                                frac=round(rach / PEAK_LANE_OPS, 4), kernel="refine_kernel<s>",
+                                                algorithmic_ops=rops))
+            if not args.no_cpu_baseline:
+                import oracle
+                hx, hy, hz = (od[c].cpu().numpy() for c in ("x", "y", "z"))
+                hp = od["pivot"].cpu().numpy()
+                tc0 = time.perf_counter()
+                done = 0
+                for i in range(16):
+                    lig = Lr.ligand(i)
+                    a0, N = int(Lr.atom_offset[i]), int(Lr.n_atoms[i])
+                    for q in range(8):
+                        b = kp * a0 + q * N
+                        pose = np.stack([hx[b:b + N], hy[b:b + N], hz[b:b + N]], 1).astype(np.float64)
+                        oracle.refine(lig, pk, pose, hp[i, q].astype(np.float64), bits=32)
+                        done += 1
+                tcs = time.perf_counter() - tc0
+                side["refine"]["cpu_baseline"] = dict(value=round(done / tcs, 2), unit="poses/s", cores=1,
+                                                      kind="oracle",
+                                                      sample=f"{done} poses (8 kept poses of each of the first 16 "
+                                                             f"ligands), {args.refine_steps} steps, FP32 oracle, "
+                                                             f"one process")
+                log(f"refine cpu baseline: {done / tcs:.1f} poses/s on one core")
             log(f"refine: {nrf * kp} poses x {args.refine_steps} steps in {rms:.1f} ms "
                 f"({nrf * kp / (rms * 1e-3):.0f} poses/s); ranking {e1.elapsed_time(e2):.3f} ms")
             del od, poses, rf, rk
