@@ -629,9 +629,15 @@ __global__ __launch_bounds__(256) void dock_plain_kernel(GridDev G, LigDev Lg, D
 }
 
 // Bucketed method: persistent; wavefronts pull (ligand, restart chunk) items of
-// one size bucket from an atomic cursor until the bucket is drained.
+// one size bucket from an atomic cursor until the bucket is drained.  Occupancy
+// target per instance (wavefronts per SIMD), chosen by measurement: the register
+// budget it implies makes the compiler spill a few values to scratch, which
+// costs less than the latency the extra wavefronts hide.
+constexpr int bucket_waves_per_simd(int nslot) { return nslot == 1 ? 6 : nslot == 2 ? 5 : 4; }
+
 template <int NSLOT, int SPL>
-__global__ __launch_bounds__(256) void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bucket_waves_per_simd(NSLOT))))
+void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
   extern __shared__ float4 lds[];
   int* tab = reinterpret_cast<int*>(lds);
   fill_brick_tables(G, tab);
