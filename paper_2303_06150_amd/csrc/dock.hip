@@ -475,7 +475,6 @@ __device__ void load_samples(const DockDev& D, SampleReg<SPL>& sm) {
 template <int NSLOT>
 struct LigReg {
   int N, K, abase, toff;
-  float x0[3][NSLOT];
   uint32_t mk[NSLOT];
   float P0[3];
 };
@@ -491,9 +490,6 @@ __device__ void load_ligand(const LigDev& Lg, int lig, LigReg<NSLOT>& L) {
   for (int s = 0; s < NSLOT; ++s) {
     const int a = s * 64 + lane;
     const bool in = a < L.N;
-    L.x0[0][s] = in ? Lg.x[L.abase + a] : 0.f;
-    L.x0[1][s] = in ? Lg.y[L.abase + a] : 0.f;
-    L.x0[2][s] = in ? Lg.z[L.abase + a] : 0.f;
     L.mk[s] = in ? Lg.mask[L.abase + a] : 0u;
   }
 #pragma unroll
@@ -502,7 +498,9 @@ __device__ void load_ligand(const LigDev& Lg, int lig, LigReg<NSLOT>& L) {
 
 // Restart placement: x = M_r (x0 - P0) + (c + t_r), pivot c + t_r.
 template <int NSLOT>
-__device__ __forceinline__ void place_pose(const DockDev& D, const LigReg<NSLOT>& L, int r, PoseReg<NSLOT>& p) {
+__device__ __forceinline__ void place_pose(const LigDev& Lg, const DockDev& D, const LigReg<NSLOT>& L, int r,
+                                           PoseReg<NSLOT>& p) {
+  const int lane = lane_id();
   const float* row = D.restarts + 12 * r;
   float m[12];
 #pragma unroll
@@ -510,7 +508,12 @@ __device__ __forceinline__ void place_pose(const DockDev& D, const LigReg<NSLOT>
   float q[3] = {D.c[0] + m[9], D.c[1] + m[10], D.c[2] + m[11]};
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
-    float vx = L.x0[0][s] - L.P0[0], vy = L.x0[1][s] - L.P0[1], vz = L.x0[2][s] - L.P0[2];
+    // the input coordinates are re-read (L2-resident) rather than held in registers
+    const int a = s * 64 + lane;
+    const bool in = a < L.N;
+    const float x0 = in ? Lg.x[L.abase + a] : 0.f, y0 = in ? Lg.y[L.abase + a] : 0.f,
+                z0 = in ? Lg.z[L.abase + a] : 0.f;
+    float vx = x0 - L.P0[0], vy = y0 - L.P0[1], vz = z0 - L.P0[2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float y = fmaf(m[3 * c + 2], vz, fmaf(m[3 * c + 1], vy, m[3 * c] * vx));
@@ -532,7 +535,7 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
   const int lane = lane_id();
   const int N = L.N;
   PoseReg<NSLOT> p;
-  place_pose(D, L, r, p);
+  place_pose(Lg, D, L, r, p);
 
   int16_t* tr = D.trace ? D.trace + ((size_t)lig * D.R + r) * (size_t)D.S * D.trace_w : nullptr;
   uint16_t* mrec = move_record(D, lig, L.toff, L.K, r);
@@ -579,7 +582,7 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
 template <int NSLOT>
 __device__ void replay_restart(const LigDev& Lg, const DockDev& D, const LigReg<NSLOT>& L, int lig, int r,
                                PoseReg<NSLOT>& p) {
-  place_pose(D, L, r, p);
+  place_pose(Lg, D, L, r, p);
   const uint16_t* mrec = move_record(D, lig, L.toff, L.K, r);
   // recorded indices are below A (rotations, torsions) and T (translations); the
   // clamps only keep table reads in range
