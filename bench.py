@@ -211,6 +211,62 @@ def experiment_clusters(lg, torch, pocket, dl, rt, at, kw, n, log):
     return dict(experiment="clusters", ligands=n, rows=rows)
 
 
+def experiment_sites(lg, torch, w, pocket, L, rt, at, kw, n_sites, n_lig, log):
+    """Sec. 5.2 docks every ligand into twelve docking sites of one target: a
+    prefix of the library docked into n_sites synthetic sites of the workload's
+    grid size, in one call (site by site, or interleaved per ligand) against one
+    single-site call per site.  Site 0 is the workload's pocket."""
+    import gen
+    t = pocket.get_tuning()
+    pockets = [pocket]
+    for s in range(1, n_sites):
+        c = (10.0 + 6.0 * np.cos(s), -4.0 + 6.0 * np.sin(s), 6.5 + 0.5 * s)
+        pk = gen.pocket(w.grid_n, w.spacing, w.n_gauss, w.n_shell, w.seed + 1000 + s, center=c)
+        p = lg.Pocket(torch.from_numpy(pk.grid).cuda(), pk.origin, pk.spacing, pk.center, pk.out_value,
+                      inv_spacing=pk.inv_spacing)
+        p.set_tuning(t)
+        pockets.append(p)
+    Ls = L.subset(np.arange(n_lig))
+    dl = lg.device_ligands(Ls.atom_offset, Ls.tors_offset, Ls.x, Ls.y, Ls.z, Ls.frag_mask, Ls.tors_atoms,
+                           Ls.inv_bond_len, Ls.ref_point)
+    rows = []
+    results = {}
+
+    def timed(label, fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            res = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 2
+        results[label] = res
+        rows.append(dict(mode=label, seconds=round(dt, 3), value=round(n_lig * n_sites / dt, 1),
+                         unit="ligand-site dockings/s"))
+        log(f"sites: {label}: {n_lig * n_sites / dt:.1f} ligand-site dockings/s")
+
+    outs = [None] * n_sites
+
+    def sequential():
+        for s, p in enumerate(pockets):
+            outs[s] = lg.lg_dock_batch(p, dl, rt, at, mode=lg.LG_BUCKETED, out=outs[s], **kw)
+        return list(outs)
+
+    timed("one call per site", sequential)
+    timed("one call, site by site", lambda: lg.lg_dock_sites(pockets, dl, rt, at, site_major=True, **kw))
+    timed("one call, interleaved", lambda: lg.lg_dock_sites(pockets, dl, rt, at, site_major=False, **kw))
+    ref = results["one call per site"]
+    same = all(torch.equal(o[k], r[k]) for label in ("one call, site by site", "one call, interleaved")
+               for o, r in zip(results[label], ref) for k in ("score", "restart_id", "x", "pivot"))
+    base = rows[0]["value"]
+    for r in rows:
+        r["speedup_vs_one_call_per_site"] = round(r["value"] / base, 3)
+    for p in pockets[1:]:
+        p.free()
+    return dict(experiment="sites", sites=n_sites, ligands=n_lig, grid=w.grid_n, results_bitwise_equal=same,
+                rows=rows)
+
+
 def cpu_baseline(w, sample_ids, procs):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import multiprocessing as mp
@@ -260,7 +316,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side-runs", action="store_true", help="skip the plain and ablation runs")
-    ap.add_argument("--experiment", choices=("bucket-size", "clusters"), default=None,
+    ap.add_argument("--sites", type=int, default=12, help="docking sites of the sites experiment")
+    ap.add_argument("--sites-ligands", type=int, default=10000, help="library prefix of the sites experiment")
+    ap.add_argument("--experiment", choices=("bucket-size", "clusters", "sites"), default=None,
                     help="run one of the paper's experiments on synthetic inputs instead of the benchmark "
                          "(prints its own JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -330,6 +388,11 @@ def main():
                     rot_bounds=list(tt.rot_bounds[:tt.n_rot_clusters]))
         log(f"autotune on {nt} ligands: {tune}")
         del dlt
+    if args.experiment == "sites":
+        print(json.dumps(experiment_sites(lg, torch, w, pocket, L, rt, at, kw, args.sites,
+                                          min(args.sites_ligands, n), log)), flush=True)
+        pocket.free()
+        return
 
     # ---- bucketed persistent path: the timed steps
     out = None

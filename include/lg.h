@@ -172,6 +172,22 @@ lg_status lg_free_pocket(lg_pocket pocket);
 lg_status lg_dock_batch(lg_pocket pocket, const lg_ligands* ligands, const lg_dock_params* params,
                         const lg_dock_out* out, void* stream);
 
+/* Dock a batch into several docking sites at once (Sec. 2: a docking site is
+ * one region of the target that ligands are docked into; the bucket-size
+ * experiments of Sec. 5.2 dock every ligand into twelve sites of one target):
+ * every ligand is docked into every site, results as lg_dock_batch with
+ * LG_BUCKETED on each site in turn (outs[s] receives site s; mode and trace
+ * are ignored).  The sites must share the first site's device, grid
+ * dimensions and spacing (their grids, origins, centres and far values may
+ * differ); the first handle's tuning and workspace are used, the workspace
+ * holding the final scores and move records of every site.
+ * Work items are (site, ligand, restart chunk): site_major != 0 takes the
+ * sites one after another, so the caches hold about one site's grid at a time;
+ * 0 interleaves the sites per ligand.  Calls on the first handle must not
+ * overlap; synchronises `stream` once (validation and the site table). */
+lg_status lg_dock_sites(const lg_pocket* pockets, int32_t n_sites, const lg_ligands* ligands,
+                        const lg_dock_params* params, const lg_dock_out* outs, int32_t site_major, void* stream);
+
 /* A library held in host memory: the lg_ligands layout with every array a
  * host pointer (no device copy needed). */
 typedef struct {

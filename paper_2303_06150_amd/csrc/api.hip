@@ -21,6 +21,8 @@ hipError_t launch_dock_plain(int nslot, int spl, int wpb, const GridDev& G, cons
 hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
                               const DockDev& D, const QueueDev& Q, hipStream_t st);
 hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int tab_len, int* blocks_per_cu);
+hipError_t launch_dock_sites(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
+                             const DockDev& D, const QueueDev& Q, const SitesDev& Sd, hipStream_t st);
 hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr);
 hipError_t launch_topk(int nslot, const LigDev& Lg, const DockDev& D, int n, int k, float* score, int32_t* rid,
                        float* ox, float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st);
@@ -863,6 +865,143 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
   }
   release();
   return s;
+}
+
+lg_status lg_dock_sites(const lg_pocket* pockets, int32_t n_sites, const lg_ligands* L, const lg_dock_params* P,
+                        const lg_dock_out* outs, int32_t site_major, void* stream) {
+  if (!pockets || !P || !outs) return fail(LG_ERR_INVALID_ARG, "pockets, params and outs must not be NULL");
+  if (n_sites < 1 || n_sites > 4096) return fail(LG_ERR_INVALID_ARG, "n_sites %d outside 1..4096", n_sites);
+  for (int si = 0; si < n_sites; ++si) {
+    if (!pockets[si]) return fail(LG_ERR_INVALID_ARG, "pocket %d is NULL", si);
+    const lg_pocket_desc& a = pockets[0]->desc;
+    const lg_pocket_desc& b = pockets[si]->desc;
+    if (pockets[si]->device != pockets[0]->device || a.nx != b.nx || a.ny != b.ny || a.nz != b.nz ||
+        a.spacing != b.spacing || a.inv_spacing != b.inv_spacing)
+      return fail(LG_ERR_INVALID_ARG, "site %d: every site needs the first site's device, dimensions and spacing", si);
+  }
+  lg_status s = check_ligands(L, true);
+  if (s != LG_OK) return s;
+  if (P->restarts < 1 || P->restarts > LG_MAX_RESTARTS) return fail(LG_ERR_LIMIT, "restarts %d outside 1..%d", P->restarts, LG_MAX_RESTARTS);
+  if (P->angle_samples < 1 || P->angle_samples > LG_MAX_SAMPLES || P->trans_samples < 1 || P->trans_samples > LG_MAX_SAMPLES)
+    return fail(LG_ERR_LIMIT, "samples per scan outside 1..%d", LG_MAX_SAMPLES);
+  if (P->sweeps < 0) return fail(LG_ERR_INVALID_ARG, "sweeps < 0");
+  if (P->top_k < 1 || P->top_k > P->restarts) return fail(LG_ERR_INVALID_ARG, "top_k %d outside 1..R", P->top_k);
+  if (!P->restart_table || !P->angle_table) return fail(LG_ERR_INVALID_ARG, "restart_table and angle_table are required");
+  if (!std::isfinite(P->trans_step) || !std::isfinite(P->clash_dist2)) return fail(LG_ERR_INVALID_ARG, "non-finite step or clash distance");
+  for (int si = 0; si < n_sites; ++si)
+    if (L->n > 0 && (!outs[si].score || !outs[si].restart_id || !outs[si].x || !outs[si].y || !outs[si].z))
+      return fail(LG_ERR_INVALID_ARG, "site %d: score, restart_id and x/y/z outputs are required", si);
+  if (L->n == 0) return LG_OK;
+  const int n = L->n, R = P->restarts;
+  const long long moves_per_site = (long long)R * P->sweeps * (6LL * n + L->total_torsions);
+  if (moves_per_site * n_sites > (1LL << 40)) return fail(LG_ERR_LIMIT, "move records of all sites too large");
+  const int chunk = pockets[0]->tuning.restart_chunk;
+  if ((long long)n * ((R + chunk - 1) / chunk) * n_sites >= (1LL << 30))
+    return fail(LG_ERR_LIMIT, "ligands x restart chunks x sites must stay below 2^30 work items");
+  lg_pocket p = pockets[0];
+  hipStream_t st = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+  const lg_tuning& tu = p->tuning;
+  const int B = tu.n_atom_clusters * tu.n_rot_clusters;
+  Layout lay;
+  const size_t o_stats = lay.take(16 * sizeof(int32_t));
+  const size_t o_final = lay.take((size_t)n * R * n_sites * sizeof(float));
+  const size_t o_moves = lay.take((size_t)moves_per_site * n_sites * sizeof(uint16_t));
+  const size_t o_cls = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_perm = lay.take((size_t)n * sizeof(int32_t));
+  const size_t o_cnt = lay.take((size_t)(4 * B + 1) * sizeof(int32_t));
+  const size_t o_grids = lay.take((size_t)n_sites * sizeof(lg::SiteGrid));
+  s = ensure_ws(p, lay.off);
+  if (s != LG_OK) return s;
+  char* ws = (char*)p->ws;
+  int max_atoms = 0, max_tors = 0;
+  s = check_on_device(p, L, (int32_t*)(ws + o_stats), st, &max_atoms, &max_tors);
+  if (s != LG_OK) return s;
+  std::vector<lg::SiteGrid> grids(n_sites);
+  for (int si = 0; si < n_sites; ++si) {
+    const lg::GridDev& g = pockets[si]->grid;
+    lg::SiteGrid& sg = grids[si];
+    sg.g0 = g.g0;
+    sg.gb = g.gb;
+    sg.gk = g.gk;
+    for (int a = 0; a < 3; ++a) {
+      sg.c0[a] = g.c0[a];
+      sg.o[a] = g.o[a];
+    }
+    sg.out = g.out;
+    for (int a = 0; a < 3; ++a) sg.c[a] = pockets[si]->desc.center[a];
+  }
+  lg::SiteGrid* dgrids = (lg::SiteGrid*)(ws + o_grids);
+  LG_HIP(hipMemcpyAsync(dgrids, grids.data(), grids.size() * sizeof(lg::SiteGrid), hipMemcpyHostToDevice, st));
+  LG_HIP(hipStreamSynchronize(st));
+
+  lg::DockDev D;
+  D.R = R;
+  D.A = P->angle_samples;
+  D.T = P->trans_samples;
+  D.S = P->sweeps;
+  D.delta = P->trans_step;
+  D.clash2 = P->clash_dist2;
+  D.clash_r2 = P->clash_dist2 > 0.f ? (std::sqrt(P->clash_dist2) + 0.05f) * (std::sqrt(P->clash_dist2) + 0.05f) : 0.f;
+  for (int a = 0; a < 3; ++a) D.c[a] = p->desc.center[a];
+  D.restarts = P->restart_table;
+  D.angles = P->angle_table;
+  D.final_scores = (float*)(ws + o_final);
+  D.moves = (uint16_t*)(ws + o_moves);
+  D.lazy_clash = tu.lazy_clash;
+  D.trace = nullptr;
+  D.trace_w = 6;
+  lg::SitesDev Sd{dgrids, n_sites, site_major ? 1 : 0, (size_t)n * R, (size_t)moves_per_site};
+  const lg::LigDev Lg = lig_dev(L);
+  const int spl = spl_for(D.A, D.T);
+  if (spl > 16) return fail(LG_ERR_LIMIT, "samples per lane %d > 16", spl);
+
+  lg::ClusterBounds cb;
+  std::memset(&cb, 0, sizeof cb);
+  cb.na = tu.n_atom_clusters;
+  cb.nr = tu.n_rot_clusters;
+  for (int c = 0; c < cb.na; ++c) cb.atom[c] = tu.atom_bounds[c];
+  for (int c = 0; c < cb.nr; ++c) cb.rot[c] = tu.rot_bounds[c];
+  cb.atom[cb.na - 1] = LG_MAX_ATOMS;
+  int32_t* cls = (int32_t*)(ws + o_cls);
+  int32_t* perm = (int32_t*)(ws + o_perm);
+  int32_t* counts = (int32_t*)(ws + o_cnt);
+  int32_t* start = counts + B;
+  int32_t* fill = start + B + 1;
+  int32_t* cursors = fill + B;
+  LG_HIP(lg::launch_bucketing(L->atom_offset, L->tors_offset, n, cb, cls, counts, start, fill, perm, cursors, st));
+  // every bucket's persistent launch on the caller's stream, largest instance first
+  for (int ca = cb.na - 1; ca >= 0; --ca) {
+    const int nslot = std::max(1, (std::min(cb.atom[ca], max_atoms) + 63) / 64);
+    const int wpb = tu.waves_per_block[nslot - 1];
+    int bpc = 0;
+    LG_HIP(lg::occupancy_dock_bucket(nslot, spl, wpb, p->grid.tab_len, &bpc));
+    if (bpc < 1) return fail(LG_ERR_DEVICE, "kernel instance (%d slots, %d samples/lane) cannot be resident", nslot, spl);
+    for (int cr = cb.nr - 1; cr >= 0; --cr) {
+      lg::QueueDev Q{perm, start, cursors, ca * cb.nr + cr, tu.restart_chunk};
+      LG_HIP(lg::launch_dock_sites(nslot, spl, wpb, bpc * p->cus * tu.grid_scale, p->grid, Lg, D, Q, Sd, st));
+    }
+  }
+  const int topk_slots = std::max(1, (max_atoms + 63) / 64);
+  for (int si = 0; si < n_sites; ++si) {
+    lg::DockDev Ds = D;
+    for (int a = 0; a < 3; ++a) Ds.c[a] = pockets[si]->desc.center[a];
+    Ds.final_scores = D.final_scores + (size_t)si * Sd.scores_stride;
+    Ds.moves = D.moves + (size_t)si * Sd.moves_stride;
+    const lg_dock_out& O = outs[si];
+    LG_HIP(lg::launch_topk(topk_slots, Lg, Ds, n, P->top_k, O.score, O.restart_id, O.x, O.y, O.z, O.all_scores,
+                           O.pivot, st));
+  }
+  // the bucket statistics and any captured single-site batch referred to the
+  // workspace contents this call replaced
+  p->launches.clear();
+  p->timed = false;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey.clear();
+  }
+  return LG_OK;
 }
 
 int32_t lg_bucket_stats(lg_pocket p, lg_bucket_stat* out, int32_t capacity) {

@@ -680,6 +680,86 @@ void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
   }
 }
 
+// Several docking sites: the bucket kernel's loop over items (site, ligand of
+// the bucket, restart chunk); each item docks against its site's grid and
+// records into the site's scores and moves.  The brick tables depend on the
+// grid dimensions only, shared by every site.
+template <int NSLOT, int SPL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bucket_waves_per_simd(NSLOT))))
+void dock_sites_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q, SitesDev Sd) {
+  extern __shared__ float4 lds[];
+  int* tab = reinterpret_cast<int*>(lds);
+  fill_brick_tables(G, tab);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * (3 * 64 * NSLOT);
+  float4* cand = scr + 64 * NSLOT;
+  const int lane = lane_id();
+  const int b0 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket]);
+  const int b1 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket + 1]);
+  const int nlig = b1 - b0;
+  const int nch = (D.R + Q.chunk - 1) / Q.chunk;
+  const long long per_site = (long long)nlig * nch;
+  const long long n_items = per_site * Sd.n_sites;
+  if (n_items == 0) return;
+  SampleReg<SPL> sm;
+  load_samples(D, sm);
+  int cur_lig = -1;
+  LigReg<NSLOT> L;
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(Q.cursor + Q.bucket, 1);
+    item = __builtin_amdgcn_readlane(item, 0);
+    if ((long long)item >= n_items) break;
+    int site, li, ch;
+    if (Sd.site_major) {
+      site = (int)(item / per_site);
+      const int rem = (int)(item - site * per_site);
+      li = rem / nch;
+      ch = rem - li * nch;
+    } else {
+      li = item / (nch * Sd.n_sites);
+      const int rem = item - li * nch * Sd.n_sites;
+      site = rem / nch;
+      ch = rem - site * nch;
+    }
+    const int lig = __builtin_amdgcn_readfirstlane(Q.perm[b0 + li]);
+    if (lig != cur_lig) {
+      load_ligand(Lg, lig, L);
+      cur_lig = lig;
+    }
+    // the site's fields as uniform words: a plain load of Sd.grids would be
+    // held in vector registers for the whole item
+    GridDev Gs = G;
+    DockDev Ds = D;
+    {
+      const int* w = reinterpret_cast<const int*>(Sd.grids + site);
+      int v[sizeof(SiteGrid) / 4];
+#pragma unroll
+      for (int k = 0; k < (int)(sizeof(SiteGrid) / 4); ++k) v[k] = __builtin_amdgcn_readfirstlane(w[k]);
+      SiteGrid sg;
+      __builtin_memcpy(&sg, v, sizeof sg);
+      Gs.g0 = sg.g0;
+      Gs.gb = sg.gb;
+      Gs.gk = sg.gk;
+      for (int a = 0; a < 3; ++a) {
+        Gs.c0[a] = sg.c0[a];
+        Gs.o[a] = sg.o[a];
+      }
+      Gs.out = sg.out;
+      for (int a = 0; a < 3; ++a) Ds.c[a] = sg.c[a];
+    }
+    Ds.final_scores = D.final_scores + (size_t)site * Sd.scores_stride;
+    Ds.moves = D.moves + (size_t)site * Sd.moves_stride;
+    const int r0 = ch * Q.chunk, r1 = min(D.R, r0 + Q.chunk);
+    if (L.N > 64 * NSLOT) {
+      for (int r = r0 + lane; r < r1; r += 64) Ds.final_scores[(size_t)lig * D.R + r] = __builtin_nanf("");
+      continue;
+    }
+    for (int r = r0; r < r1; ++r) dock_restart(Gs, Lg, Ds, sm, L, lig, r, scr, cand, tab);
+  }
+}
+
 // Per-ligand top-k over restarts (score descending, equal scores: lower r);
 // the kept poses and pivots rebuilt from their recorded moves.  One wavefront
 // per ligand.
@@ -767,6 +847,18 @@ hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const Gri
   {                                                                                             \
     hipLaunchKernelGGL((dock_bucket_kernel<NS, SP>), dim3(blocks), dim3(64 * wpb),              \
                        lds_bytes(NS, wpb, G.tab_len), st, G, Lg, D, Q);                                \
+    return hipGetLastError();                                                                   \
+  }
+  LG_DISPATCH(nslot, spl, CALL)
+#undef CALL
+}
+
+hipError_t launch_dock_sites(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
+                             const DockDev& D, const QueueDev& Q, const SitesDev& Sd, hipStream_t st) {
+#define CALL(NS, SP)                                                                            \
+  {                                                                                             \
+    hipLaunchKernelGGL((dock_sites_kernel<NS, SP>), dim3(blocks), dim3(64 * wpb),               \
+                       lds_bytes(NS, wpb, G.tab_len), st, G, Lg, D, Q, Sd);                     \
     return hipGetLastError();                                                                   \
   }
   LG_DISPATCH(nslot, spl, CALL)

@@ -74,6 +74,32 @@ struct RefineDev {
   float* score;
 };
 
+// What differs between sites that share grid dimensions and spacing: the
+// grid copies, the origin (and the nearest-node offsets built from it), the
+// value outside the box and the site centre that placement moves ligands to.
+// Sixteen 32-bit words, read into scalar registers.
+struct SiteGrid {
+  const float* g0;
+  const char* gb;
+  const char* gk;
+  float c0[3];
+  float o[3];
+  float out;
+  float c[3];
+};
+
+// Several docking sites in one launch: grids of identical dimensions and
+// spacing (so one set of brick tables serves all); per site its own final
+// scores and move records.  Items are (site, ligand, chunk), site by site or
+// with the sites interleaved per ligand.
+struct SitesDev {
+  const SiteGrid* grids;    // device [n_sites]
+  int n_sites;
+  int site_major;           // 1: site by site; 0: every site of a ligand in turn
+  size_t scores_stride;     // floats of final scores per site
+  size_t moves_stride;      // move-record entries per site
+};
+
 // Persistent work source of one bucket: items are (ligand of the bucket,
 // chunk of `chunk` restarts), pulled from `cursor` by whole wavefronts.
 struct QueueDev {

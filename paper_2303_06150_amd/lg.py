@@ -25,8 +25,8 @@ LG_NEAREST, LG_TRILINEAR = 0, 1
 LG_PLAIN, LG_BUCKETED = 0, 1
 LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
 
-EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_stream", "lg_score", "lg_refine", "lg_rank",
-           "lg_autotune",
+EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_sites", "lg_dock_stream", "lg_score",
+           "lg_refine", "lg_rank", "lg_autotune",
            "lg_set_tuning", "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
            "lg_last_error", "lg_version")
 
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
     lib.lg_load_pocket.argtypes = [P(lg_pocket_desc), c_void_p, c_int32, c_void_p, P(c_void_p)]
     lib.lg_free_pocket.argtypes = [c_void_p]
     lib.lg_dock_batch.argtypes = [c_void_p, P(lg_ligands), P(lg_dock_params), P(lg_dock_out), c_void_p]
+    lib.lg_dock_sites.argtypes = [P(c_void_p), c_int32, P(lg_ligands), P(lg_dock_params), P(lg_dock_out), c_int32,
+                                  c_void_p]
     lib.lg_dock_stream.argtypes = [c_void_p, P(lg_host_ligands), P(lg_dock_params), c_int32, P(lg_host_out),
                                    c_void_p]
     lib.lg_score.argtypes = [c_void_p, P(lg_ligands), c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
@@ -132,8 +134,8 @@ def load_library(path: str = LIB_PATH):
     lib.lg_atom_clusters.argtypes = [c_int32, c_int32, c_int32, P(c_int32)]
     lib.lg_rotamer_clusters.argtypes = [c_int32, c_int32, P(c_int32)]
     lib.lg_last_error.restype = ctypes.c_char_p
-    for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_stream", "lg_score", "lg_refine", "lg_rank",
-                 "lg_autotune", "lg_set_tuning", "lg_get_tuning"):
+    for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_sites", "lg_dock_stream", "lg_score",
+                 "lg_refine", "lg_rank", "lg_autotune", "lg_set_tuning", "lg_get_tuning"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -313,6 +315,37 @@ def lg_dock_batch(pocket: Pocket, ligs: DeviceLigands, restart_table, angle_tabl
     _check(_lib.lg_dock_batch(pocket.handle, ctypes.byref(L), ctypes.byref(params), ctypes.byref(o),
                               _stream_handle(stream)))
     return out
+
+
+def lg_dock_sites(pockets, ligs: DeviceLigands, restart_table, angle_table, *, sweeps: int, top_k: int,
+                  trans_samples: int, trans_step: float, clash_dist2: float, site_major: bool = True,
+                  want_all_scores=False, stream=None):
+    """Dock a batch into every site of `pockets` (same grid dimensions and
+    spacing) in one call.  Returns one dict per site, as lg_dock_batch."""
+    torch = _torch()
+    R, A = int(restart_table.shape[0]), int(angle_table.shape[0])
+    n, TA, dev = ligs.n, ligs.total_atoms, ligs.x.device
+    outs = []
+    for _ in pockets:
+        o = dict(score=torch.empty((n, top_k), dtype=torch.float32, device=dev),
+                 restart_id=torch.empty((n, top_k), dtype=torch.int32, device=dev),
+                 x=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
+                 y=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
+                 z=torch.empty(top_k * TA, dtype=torch.float32, device=dev),
+                 pivot=torch.empty((n, top_k, 3), dtype=torch.float32, device=dev))
+        if want_all_scores:
+            o["all_scores"] = torch.empty((n, R), dtype=torch.float32, device=dev)
+        outs.append(o)
+    params = lg_dock_params(R, A, int(trans_samples), int(sweeps), int(top_k), LG_BUCKETED, float(trans_step),
+                            float(clash_dist2), _ptr(restart_table), _ptr(angle_table))
+    O = (lg_dock_out * len(pockets))(*[
+        lg_dock_out(_ptr(o["score"]), _ptr(o["restart_id"]), _ptr(o["x"]), _ptr(o["y"]), _ptr(o["z"]),
+                    _ptr(o.get("all_scores")), None, 0, _ptr(o["pivot"])) for o in outs])
+    H = (c_void_p * len(pockets))(*[p.handle.value for p in pockets])
+    L = ligs.struct()
+    _check(_lib.lg_dock_sites(H, len(pockets), ctypes.byref(L), ctypes.byref(params), O, int(bool(site_major)),
+                              _stream_handle(stream)))
+    return outs
 
 
 def lg_dock_stream(pocket: Pocket, atom_offset, tors_offset, x, y, z, frag_mask, tors_atoms, inv_bond_len,
