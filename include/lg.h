@@ -87,7 +87,8 @@ typedef struct lg_pocket_s* lg_pocket;
  *                     consistency, local ids), so bad device data is reported
  *                     as LG_ERR_INVALID_ARG / LG_ERR_LIMIT, never docked.
  * Limits: 1 <= atoms <= LG_MAX_ATOMS and 0 <= bonds <= LG_MAX_TORSIONS per
- * ligand; local ids in range. */
+ * ligand; local ids in range; total_atoms <= 2^30 - 256 per batch (the
+ * kernels address the atom arrays with 32-bit byte offsets). */
 typedef struct {
   int32_t n;
   int32_t total_atoms;

@@ -164,6 +164,8 @@ lg_status check_ligands(const lg_ligands* L, bool need_tors) {
   if (need_tors && (!L->frag_mask || (L->total_torsions > 0 && (!L->tors_atoms || !L->inv_bond_len))))
     return fail(LG_ERR_INVALID_ARG, "a required ligand array is NULL");
   if (L->total_atoms < L->n || L->total_torsions < 0) return fail(LG_ERR_INVALID_ARG, "bad total sizes");
+  if (L->total_atoms > (1 << 30) - 256)
+    return fail(LG_ERR_LIMIT, "total_atoms %d above 2^30 - 256 (32-bit byte offsets)", L->total_atoms);
   if (L->atom_offset_host) {
     for (int i = 0; i < L->n; ++i) {
       int N = L->atom_offset_host[i + 1] - L->atom_offset_host[i];

@@ -116,6 +116,9 @@ __device__ __forceinline__ void apply_trans(const DockDev& D, PoseReg<NSLOT>& p,
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) p.x[E][s] = p.x[E][s] + dd;
   p.piv[E] = p.piv[E] + dd;
+  // update the pivot here: left to itself the compiler sinks this add past the
+  // torsion scans and keeps dd alive (in scratch) until then
+  asm volatile("" : "+v"(p.piv[E]));
 }
 
 // Bond k's axis at the current pose: pivot atom a, unit direction u.
@@ -508,11 +511,16 @@ __device__ __forceinline__ void place_pose(const LigDev& Lg, const DockDev& D, c
   float q[3] = {D.c[0] + m[9], D.c[1] + m[10], D.c[2] + m[11]};
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
-    // the input coordinates are re-read (L2-resident) rather than held in registers
+    // the input coordinates are re-read (L2-resident) rather than held in
+    // registers, through one 32-bit byte offset on the scalar bases: 64-bit
+    // per-lane addresses would be hoisted out of the restart loop and spilled
     const int a = s * 64 + lane;
     const bool in = a < L.N;
-    const float x0 = in ? Lg.x[L.abase + a] : 0.f, y0 = in ? Lg.y[L.abase + a] : 0.f,
-                z0 = in ? Lg.z[L.abase + a] : 0.f;
+    uint32_t off = (uint32_t)(L.abase + a) * 4u;
+    asm volatile("" : "+v"(off));   // computed here, per restart
+    const float x0 = in ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(Lg.x) + off) : 0.f;
+    const float y0 = in ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(Lg.y) + off) : 0.f;
+    const float z0 = in ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(Lg.z) + off) : 0.f;
     float vx = x0 - L.P0[0], vy = y0 - L.P0[1], vz = z0 - L.P0[2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
