@@ -30,11 +30,11 @@ __device__ __forceinline__ void move_cos_sin(float x, float& c, float& s) {
   }
 }
 
-// Torsions deepest first, then rotation by |w| about w/|w| through the pivot,
-// then + t (pivot included).  q holds t[3], w[3]; th the bond angles.
+// Torsions deepest first, each about the bond axis at that moment.  th holds
+// the bond angles.
 template <int NSLOT, bool LIB = false>
-__device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
-                           const float* inv_len, const float* q, const float* th) {
+__device__ void apply_torsions(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
+                               const float* inv_len, const float* th) {
   const int lane = lane_id();
   for (int k = K - 1; k >= 0; --k) {
     const float ang = th[k];
@@ -60,6 +60,12 @@ __device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int
       }
     }
   }
+}
+
+// Rotation by |w| about w/|w| through the pivot, then + t (pivot included).
+// q holds t[3], w[3].
+template <int NSLOT, bool LIB = false>
+__device__ void apply_rigid(MoveState<NSLOT>& p, const float* q) {
   const float w2 = fmaf(q[5], q[5], fmaf(q[4], q[4], q[3] * q[3]));
   if (w2 > 0.f) {
     const float w = sqrtf(w2);
@@ -83,25 +89,100 @@ __device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int
   }
 }
 
+// The local move: torsions deepest first, rotation about the pivot, translation.
+template <int NSLOT, bool LIB = false>
+__device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
+                           const float* inv_len, const float* q, const float* th) {
+  apply_torsions<NSLOT, LIB>(p, mk, N, K, tors, inv_len, th);
+  apply_rigid<NSLOT, LIB>(p, q);
+}
+
+// Bond k's axis at the pose held in pos, computed by lane k: pivot atom a_k and
+// unit direction (b_k - a_k) / |b_k - a_k| (the stored inverse length).
+struct LaneAxis {
+  float xa, ya, za, ux, uy, uz;
+};
+
+__device__ __forceinline__ LaneAxis lane_axis(const float4* pos, const int2* tors, const float* inv_len, int K) {
+  LaneAxis ax{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int k = lane_id();
+  if (k < K) {
+    const int2 t = tors[k];
+    const float4 pa = pos[t.x], pb = pos[t.y];
+    const float il = inv_len[k];
+    ax.xa = pa.x;
+    ax.ya = pa.y;
+    ax.za = pa.z;
+    ax.ux = (pb.x - pa.x) * il;
+    ax.uy = (pb.y - pa.y) * il;
+    ax.uz = (pb.z - pa.z) * il;
+  }
+  return ax;
+}
+
+// Does a torsion ever move the axis atoms of a shallower bond?  When no bond j
+// moves a_k or b_k of a bond k < j (bonds listed parents first, as a preorder
+// numbering gives), every axis that the deepest-first sequence uses is the axis
+// at the start of the move, so all torsion matrices can be built at once.
+__device__ __forceinline__ bool axes_fixed_under_torsions(const LigDev& P, int abase, int toff, int K) {
+  const int k = lane_id();
+  bool moved = false;
+  if (k < K && k + 1 < 32) {
+    const int a = P.tors_atoms[2 * (toff + k)], b = P.tors_atoms[2 * (toff + k) + 1];
+    moved = ((P.mask[abase + a] | P.mask[abase + b]) >> (k + 1)) != 0u;
+  }
+  return !wave_any(moved);
+}
+
+// Torsions deepest first with matrices built beforehand: rows r of bond k at
+// mats[3k + r] = (m[3r], m[3r+1], m[3r+2], pivot coordinate r).  Valid when the
+// axes stay fixed under the torsions (axes_fixed_under_torsions).
+template <int NSLOT>
+__device__ void apply_torsions_table(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K,
+                                     const int2* tors, const float* th, const float4* mats) {
+  const int lane = lane_id();
+  for (int k = K - 1; k >= 0; --k) {
+    const float ang = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(th[k])));
+    if (ang == 0.f) continue;
+    const int b = __builtin_amdgcn_readfirstlane(tors[k].y);
+    const float4 r0 = mats[3 * k], r1 = mats[3 * k + 1], r2 = mats[3 * k + 2];
+    const float m[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      const int at = sl * 64 + lane;
+      if (at < N && ((mk[sl] >> k) & 1u) && at != b) {
+        float y0, y1, y2;
+        mat_apply(m, p.x[0][sl] - r0.w, p.x[1][sl] - r1.w, p.x[2][sl] - r2.w, y0, y1, y2);
+        p.x[0][sl] = r0.w + y0;
+        p.x[1][sl] = r1.w + y1;
+        p.x[2][sl] = r2.w + y2;
+      }
+    }
+  }
+}
+
 // Per-atom columns summed in atom order through an LDS tile: the wavefront
 // writes the columns of 64 atoms (one slot) as tile[column * TILE_STRIDE + lane],
-// then lane c adds column c's values atom by atom.  Each column's sum runs
-// over atoms 0..N-1 in order, like a sequential loop, but all columns at once.
+// then lane c adds column c's values atom by atom, four per LDS read.  Each
+// column's sum runs over atoms 0..N-1 in order, like a sequential loop, but all
+// columns at once.
 constexpr int TILE_COLS = 16;                      // LDS per wavefront stays small (occupancy)
-constexpr int TILE_STRIDE = 65;                    // odd stride: conflict-free rows and columns
+constexpr int TILE_STRIDE = 68;                    // 16-byte aligned columns for 4-float reads
 constexpr int TILE_FLOATS = TILE_COLS * TILE_STRIDE;
 constexpr int GRAD_COLS = 7 + 3 * 32;              // score, force, torque, 3 per bond
 constexpr int GRAD_RES_FLOATS = 104;               // GRAD_COLS rounded up to float4
 constexpr int GRAD_LDS_FLOAT4 = (TILE_FLOATS + GRAD_RES_FLOATS) / 4;
+static_assert(TILE_FLOATS >= 12 * 32, "the torsion matrices reuse the tile");
 
 // Trilinear score and its gradient with respect to the local move at zero;
 // sums in atom order.  g_out: t[3], w[3], then theta[K] into th_grad.  Column
 // 0 is the score, 1..3 the force, 4..6 the torque about the pivot, 7 + 3k + d
-// component d of bond k's torque about its pivot atom over F_k.
+// component d of bond k's torque about its pivot atom over F_k.  pos holds the
+// pose p; lane k holds bond k's axis.
 template <int NSLOT>
 __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N,
-                               int K, const int2* tors, const float* inv_len, float* g_out, float* th_grad,
-                               float* tile, float* res) {
+                               int K, const int2* tors, const float4* pos, const LaneAxis& ax, float* g_out,
+                               float* th_grad, float* tile, float* res) {
   const int lane = lane_id();
   float v[NSLOT], g[3][NSLOT];
 #pragma unroll
@@ -133,10 +214,9 @@ __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, cons
       }
       for (int kk = 0; kk < nb; ++kk) {
         const int k = k0 + kk;
-        const int a = tors[k].x;
-        const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
+        const float4 pa = pos[tors[k].x];   // pivot atom a_k, the same address in every lane
         const bool in = (mk[s] >> k) & 1u;
-        const float r0 = p.x[0][s] - xa, r1 = p.x[1][s] - ya, r2 = p.x[2][s] - za;
+        const float r0 = p.x[0][s] - pa.x, r1 = p.x[1][s] - pa.y, r2 = p.x[2][s] - pa.z;
         float* t = tile + (base + 3 * kk) * TILE_STRIDE + lane;
         t[0] = in ? r1 * g[2][s] - r2 * g[1][s] : 0.f;
         t[TILE_STRIDE] = in ? r2 * g[0][s] - r0 * g[2][s] : 0.f;
@@ -145,7 +225,15 @@ __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, cons
       wave_sync();
       if (lane < ncol) {
         const float* col = tile + lane * TILE_STRIDE;
-        for (int l = 0; l < cnt; ++l) acc = acc + col[l];
+        int l = 0;
+        for (; l + 4 <= cnt; l += 4) {
+          const float4 q4 = *reinterpret_cast<const float4*>(col + l);
+          acc = acc + q4.x;
+          acc = acc + q4.y;
+          acc = acc + q4.z;
+          acc = acc + q4.w;
+        }
+        for (; l < cnt; ++l) acc = acc + col[l];
       }
       wave_sync();
     }
@@ -155,14 +243,9 @@ __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, cons
   wave_sync();
 #pragma unroll
   for (int d = 0; d < 6; ++d) g_out[d] = res[1 + d];
-  for (int k = 0; k < K; ++k) {
-    const int a = tors[k].x, b = tors[k].y;
-    const float xa = atom_value(p.x[0], a), ya = atom_value(p.x[1], a), za = atom_value(p.x[2], a);
-    const float il = inv_len[k];
-    const float ux = (atom_value(p.x[0], b) - xa) * il, uy = (atom_value(p.x[1], b) - ya) * il,
-                uz = (atom_value(p.x[2], b) - za) * il;
-    const float* t = res + 7 + 3 * k;
-    if (lane == 0) th_grad[k] = ux * t[0] + uy * t[1] + uz * t[2];
+  if (lane < K) {
+    const float* t = res + 7 + 3 * lane;
+    th_grad[lane] = ax.ux * t[0] + ax.uy * t[1] + ax.uz * t[2];
   }
   return res[0];
 }
@@ -174,46 +257,72 @@ __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, cons
 // d = 1 .. N/2 (for even N the pair at d = N/2 only from its lower end).  The
 // distance test comes first; the bond rule is evaluated only for pairs inside
 // the clash distance, which are few (bonded neighbours).
+__device__ __forceinline__ bool pair_changes(uint32_t mi, uint32_t mj, int i, int j, const int2* tors) {
+  bool changes = false;
+  for (uint32_t m = mi ^ mj; m != 0u && !changes; m &= m - 1u) {
+    const int k = __builtin_ctz(m);
+    const int mover = ((mi >> k) & 1u) ? i : j;
+    const int other = mover == i ? j : i;
+    changes = mover != tors[k].y && other != tors[k].x;
+  }
+  return changes;
+}
+
 template <int NSLOT>
 __device__ bool move_clash_free(const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N,
                                 const int2* tors, const float4* pos, float clash2) {
   const int lane = lane_id();
   bool clash = false;
   const int half = N >> 1;
-  for (int d = 1; d <= half; ++d) {
+  const int full = (N - 1) >> 1;   // distances taken from both ends' lower atom: all of 1 .. (N-1)/2
 #pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      if (s * 64 >= N) break;
-      const int i = s * 64 + lane;
-      int j = i + d;
-      if (j >= N) j -= N;
-      if (i >= N || (2 * d == N && i >= d)) continue;
-      const float4 pj = pos[j];
-      const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
-      if (!(fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2)) continue;
-      const uint32_t mj = __float_as_uint(pj.w);
-      bool changes = false;
-      for (uint32_t m = mk[s] ^ mj; m != 0u && !changes; m &= m - 1u) {
-        const int k = __builtin_ctz(m);
-        const int mover = ((mk[s] >> k) & 1u) ? i : j;
-        const int other = mover == i ? j : i;
-        changes = mover != tors[k].y && other != tors[k].x;
+  for (int s = 0; s < NSLOT; ++s) {
+    if (s * 64 >= N) break;
+    const int i = s * 64 + lane;
+    if (i < N) {
+      int j = i;
+      for (int d = 1; d <= full; ++d) {
+        j = j + 1 == N ? 0 : j + 1;
+        const float4 pj = pos[j];
+        const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
+        if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2)
+          clash |= pair_changes(mk[s], __float_as_uint(pj.w), i, j, tors);
       }
-      clash |= changes;
+      if (half > full && i < half) {   // even N: the opposite atom, from the lower end only
+        j = i + half;
+        const float4 pj = pos[j];
+        const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
+        if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2)
+          clash |= pair_changes(mk[s], __float_as_uint(pj.w), i, j, tors);
+      }
     }
   }
   return !wave_any(clash);
 }
 
 template <int NSLOT>
+__device__ __forceinline__ void store_pose(float4* pos, const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT],
+                                           int N) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s)
+    if (s * 64 + lane < N) pos[s * 64 + lane] = make_float4(p.x[0][s], p.x[1][s], p.x[2][s], __uint_as_float(mk[s]));
+}
+
+// LDS of one refinement wavefront in float4: pose, bond atoms, 1/lengths, bond
+// steps, bond gradients, gradient tile and results.
+constexpr int refine_wave_float4(int nslot) { return 64 * nslot + 16 + 8 + 8 + 8 + GRAD_LDS_FLOAT4; }
+
+template <int NSLOT>
 __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, RefineDev Rp, int n) {
   extern __shared__ float4 lds[];
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
-  float4* pos = lds + (size_t)wave * (64 * NSLOT + 32 + GRAD_LDS_FLOAT4);
+  float4* pos = lds + (size_t)wave * refine_wave_float4(NSLOT);
   int2* tors = reinterpret_cast<int2*>(pos + 64 * NSLOT);     // 32 entries (16 float4)
   float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries (8 float4)
-  float* th = inv_len + 32;                                   // 32 bond gradients / steps (8 float4)
-  float* tile = th + 32;                                      // column sums of the gradient
+  float* th = inv_len + 32;                                   // 32 bond steps (8 float4)
+  float* thg = th + 32;                                       // 32 bond gradients (8 float4)
+  float* tile = thg + 32;                                     // column sums of the gradient; then the torsion matrices
   float* res = tile + TILE_FLOATS;
   const int w = blockIdx.x * nwaves + wave;   // pose: member w % kpl of the launch's ligand w / kpl
   if (w >= n) return;
@@ -229,6 +338,7 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
     tors[lane] = make_int2(P.tors_atoms[2 * (toff + lane)], P.tors_atoms[2 * (toff + lane) + 1]);
     inv_len[lane] = P.inv_len[toff + lane];
   }
+  const bool table = axes_fixed_under_torsions(P, abase, toff, K);
   MoveState<NSLOT> cur, best;
   uint32_t mk[NSLOT];
 #pragma unroll
@@ -250,9 +360,24 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   float best_s = atom_order_sum(v, N);
   float scale = 1.f;
   float g[6];
+  LaneAxis ax;
+  // fresh: cur changed since the last gradient (a rejected step keeps the pose,
+  // so its gradient is reused); pending: cur was accepted and not yet compared
+  // with the best -- the gradient pass's column 0 is its score
+  bool fresh = true, pending = false;
   for (int step = 0; step < Rp.steps; ++step) {
-    move_gradient(G, cur, mk, N, K, tors, inv_len, g, th, tile, res);
-    wave_sync();
+    if (fresh) {
+      store_pose(pos, cur, mk, N);
+      wave_sync();
+      ax = lane_axis(pos, tors, inv_len, K);
+      const float sc = move_gradient(G, cur, mk, N, K, tors, pos, ax, g, thg, tile, res);
+      wave_sync();
+      if (pending && sc > best_s) {
+        best_s = sc;
+        best = cur;
+      }
+      fresh = pending = false;
+    }
     float q[6];
     float dt[3], dw[3];
 #pragma unroll
@@ -266,17 +391,33 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
       q[d] = (dt[d] * ft) * scale;
       q[3 + d] = (dw[d] * fw) * scale;
     }
-    for (int k = 0; k < K; ++k) {
-      float t = Rp.eta_th * th[k];
+    // bond k's step by lane k; with fixed axes also its matrix, into the tile
+    float thk = 0.f;
+    if (lane < K) {
+      float t = Rp.eta_th * thg[lane];
       t = fminf(fmaxf(t, -Rp.clip_th), Rp.clip_th);
-      if (lane == 0) th[k] = t * scale;
+      thk = t * scale;
+      th[lane] = thk;
     }
-    wave_sync();
     MoveState<NSLOT> cand = cur;
-    apply_move(cand, mk, N, K, tors, inv_len, q, th);
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s)
-      if (s * 64 + lane < N) pos[s * 64 + lane] = make_float4(cand.x[0][s], cand.x[1][s], cand.x[2][s], __uint_as_float(mk[s]));
+    if (table) {
+      float4* mats = reinterpret_cast<float4*>(tile);
+      if (lane < K && thk != 0.f) {
+        float c, sn, m[9];
+        step_cos_sin(thk, c, sn);
+        torsion_matrix(ax.ux, ax.uy, ax.uz, c, sn, m);
+        mats[3 * lane] = make_float4(m[0], m[1], m[2], ax.xa);
+        mats[3 * lane + 1] = make_float4(m[3], m[4], m[5], ax.ya);
+        mats[3 * lane + 2] = make_float4(m[6], m[7], m[8], ax.za);
+      }
+      wave_sync();
+      apply_torsions_table(cand, mk, N, K, tors, th, mats);
+    } else {
+      wave_sync();
+      apply_torsions(cand, mk, N, K, tors, inv_len, th);
+    }
+    apply_rigid(cand, q);
+    store_pose(pos, cand, mk, N);
     wave_sync();
     const bool ok = move_clash_free(cand, mk, N, tors, pos, Rp.clash2);
     wave_sync();
@@ -285,6 +426,9 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
       continue;
     }
     cur = cand;
+    fresh = pending = true;
+  }
+  if (pending) {   // the last step's accepted pose
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) v[s] = (s * 64 + lane < N) ? trilinear(G, cur.x[0][s], cur.x[1][s], cur.x[2][s], nullptr) : 0.f;
     const float sc = atom_order_sum(v, N);
@@ -317,8 +461,8 @@ __global__ __launch_bounds__(256) void score_moves_kernel(GridDev G, LigDev P, c
                                                           float* score, float* grad) {
   extern __shared__ float4 lds[];
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
-  float4* base = lds + (size_t)wave * (32 + GRAD_LDS_FLOAT4);
-  int2* tors = reinterpret_cast<int2*>(base);                 // 32 entries
+  float4* pos = lds + (size_t)wave * (64 * NSLOT + 32 + GRAD_LDS_FLOAT4);
+  int2* tors = reinterpret_cast<int2*>(pos + 64 * NSLOT);     // 32 entries
   float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries
   float* th = inv_len + 32;                                   // 32 entries
   float* tile = th + 32;
@@ -353,9 +497,11 @@ __global__ __launch_bounds__(256) void score_moves_kernel(GridDev G, LigDev P, c
   for (int d = 0; d < 3; ++d) p.piv[d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.ref[3 * i + d])));
   wave_sync();
   apply_move<NSLOT, true>(p, mk, N, K, tors, inv_len, q, th);
+  store_pose(pos, p, mk, N);
   float g[6];
   wave_sync();
-  const float sc = move_gradient(G, p, mk, N, K, tors, inv_len, g, th, tile, res);
+  const LaneAxis ax = lane_axis(pos, tors, inv_len, K);
+  const float sc = move_gradient(G, p, mk, N, K, tors, pos, ax, g, th, tile, res);
   wave_sync();
   if (lane == 0) score[i] = sc;
   if (!grad) return;
@@ -393,7 +539,7 @@ hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, cons
   if (n == 0) return hipSuccess;
   const int wpb = 4;
   const dim3 grid((n + wpb - 1) / wpb), block(64 * wpb);
-  const size_t lds = (size_t)wpb * (32 + GRAD_LDS_FLOAT4) * sizeof(float4);
+  const size_t lds = (size_t)wpb * (64 * nslot + 32 + GRAD_LDS_FLOAT4) * sizeof(float4);
   switch (nslot) {
     case 1: hipLaunchKernelGGL(score_moves_kernel<1>, grid, block, lds, st, G, P, moves, n, score, grad); break;
     case 2: hipLaunchKernelGGL(score_moves_kernel<2>, grid, block, lds, st, G, P, moves, n, score, grad); break;
@@ -404,9 +550,7 @@ hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, cons
   return hipGetLastError();
 }
 
-static size_t refine_lds(int nslot, int wpb) {
-  return (size_t)wpb * (64 * nslot + 32 + GRAD_LDS_FLOAT4) * sizeof(float4);
-}
+static size_t refine_lds(int nslot, int wpb) { return (size_t)wpb * refine_wave_float4(nslot) * sizeof(float4); }
 
 hipError_t launch_refine(int nslot, const GridDev& G, const LigDev& P, const RefineDev& Rp, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;

@@ -222,18 +222,10 @@ def device_ligands_ok(lg, L):
                              L.inv_bond_len, L.ref_point)
 
 
-def test_refine_matches_oracle(lgmod, tiny):
-    """lg_refine on docked poses: best pose and score bitwise equal to the FP32
-    oracle's refinement (same step script, same step polynomial, sums in atom
-    order)."""
-    lg = lgmod
+def refine_against_oracle(lg, pocket, pk, L, out, k):
+    """lg_refine on every ligand's top-k docked poses; best pose and score must
+    equal the FP32 oracle's refinement bitwise.  Returns how many poses moved."""
     import torch
-    w, pk, L = tiny["w"], tiny["pocket"], tiny["ligs"]
-    pocket = device_pocket(pk)
-    k = 2
-    out = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], T=w.angle_samples, S=w.sweeps, top_k=k, mode=lg.LG_BUCKETED,
-                   trace=False, all_scores=False)
-    # poses batch: every ligand's top-k poses, pivot = FP32 centroid of the pose
     parts, idx = [], []
     for i in range(L.n):
         for q in range(k):
@@ -245,6 +237,7 @@ def test_refine_matches_oracle(lgmod, tiny):
             idx.append(i)
     Lp = L.subset(np.array(idx))
     xyz_all = np.concatenate(parts)
+    # pivot = FP32 centroid of the pose
     cen = np.stack([p.astype(np.float64).mean(0) for p in parts]).astype(np.float32)
     dl = lg.device_ligands(Lp.atom_offset, Lp.tors_offset, xyz_all[:, 0], xyz_all[:, 1], xyz_all[:, 2],
                            Lp.frag_mask, Lp.tors_atoms, Lp.inv_bond_len, cen.reshape(-1))
@@ -261,7 +254,61 @@ def test_refine_matches_oracle(lgmod, tiny):
         np.testing.assert_array_equal(got, best, err_msg=f"refined pose {j}")
         assert rs[j] == s, (j, rs[j], s)
         moved += not np.array_equal(best, parts[j].astype(np.float64))
-    assert moved > Lp.n // 2
+    return moved, Lp.n
+
+
+def test_refine_matches_oracle(lgmod, tiny):
+    """lg_refine on docked poses: best pose and score bitwise equal to the FP32
+    oracle's refinement (same step script, same step polynomial, sums in atom
+    order)."""
+    lg = lgmod
+    w, pk, L = tiny["w"], tiny["pocket"], tiny["ligs"]
+    pocket = device_pocket(pk)
+    k = 2
+    out = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], T=w.angle_samples, S=w.sweeps, top_k=k, mode=lg.LG_BUCKETED,
+                   trace=False, all_scores=False)
+    moved, n = refine_against_oracle(lg, pocket, pk, L, out, k)
+    assert moved > n // 2
+    pocket.free()
+
+
+def reversed_bonds(L):
+    """The same ligands with their rotatable bonds listed in reverse (children
+    before parents): frag_mask bits, bond atoms and lengths permuted alike."""
+    parts = []
+    for i in range(L.n):
+        a = L.ligand_arrays(i)
+        K = len(a["inv_bond_len"])
+        m = np.asarray(a["frag_mask"], np.uint32)
+        rm = np.zeros_like(m)
+        for k in range(K):
+            rm |= ((m >> np.uint32(k)) & np.uint32(1)) << np.uint32(K - 1 - k)
+        a = dict(a, frag_mask=rm, tors_atoms=np.asarray(a["tors_atoms"]).reshape(-1, 2)[::-1].reshape(-1).copy(),
+                 inv_bond_len=np.asarray(a["inv_bond_len"])[::-1].copy(),
+                 inv_bond_len64=np.asarray(a["inv_bond_len64"])[::-1].copy())
+        parts.append(a)
+    return gen._assemble(L.ids, parts)
+
+
+def test_bonds_in_any_order(lgmod, tiny):
+    """Bonds listed children first: a torsion then moves the axes of bonds
+    applied after it, so refinement must take its sequential path (matrices
+    cannot be built up front).  Docking and refinement still match the oracle
+    bitwise."""
+    lg = lgmod
+    w, pk = tiny["w"], tiny["pocket"]
+    L = reversed_bonds(tiny["ligs"].subset(np.arange(24)))
+    assert (L.n_tors >= 2).sum() >= 12
+    pocket = device_pocket(pk)
+    k = 2
+    out = dock_gpu(pocket, L, tiny["r32"], tiny["a32"], T=w.angle_samples, S=w.sweeps, top_k=k, mode=lg.LG_BUCKETED,
+                   trace=True, all_scores=True)
+    rows = np.arange(w.restarts)
+    for i in range(0, L.n, 3):
+        ref = dock_oracle(pk, L, i, tiny["r32"], tiny["a32"], T=w.angle_samples, S=w.sweeps)
+        compare_ligand(out, L, i, ref, rows, k, w.restarts, "reversed bonds")
+    moved, n = refine_against_oracle(lg, pocket, pk, L, out, k)
+    assert moved > n // 2
     pocket.free()
 
 
