@@ -252,11 +252,12 @@ __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, cons
 
 // Refinement clash rule: every pair that some bond's torsion moves -- exactly one
 // of the two in F_k, the moving one not b_k, the other not a_k -- at squared
-// distance >= clash2.  `pos` holds the pose (xyz, mask bits in w) in LDS.  Each
-// unordered pair is visited once: the lane's atom i with atom (i + d) mod N for
-// d = 1 .. N/2 (for even N the pair at d = N/2 only from its lower end).  The
-// distance test comes first; the bond rule is evaluated only for pairs inside
-// the clash distance, which are few (bonded neighbours).
+// distance >= clash2.  `pos` holds the pose (xyz, mask bits in w) in LDS,
+// followed by a copy of its first (N - 1) / 2 atoms, so atom (i + d) mod N sits
+// at pos[i + d].  Each unordered pair is visited once: the lane's atom i with
+// atom i + d for d = 1 .. N/2 (for even N the pair at d = N/2 only from its
+// lower end).  The distance test comes first; the bond rule is evaluated only
+// when some lane holds a pair inside the clash distance (bonded neighbours).
 __device__ __forceinline__ bool pair_changes(uint32_t mi, uint32_t mj, int i, int j, const int2* tors) {
   bool changes = false;
   for (uint32_t m = mi ^ mj; m != 0u && !changes; m &= m - 1u) {
@@ -274,27 +275,40 @@ __device__ bool move_clash_free(const MoveState<NSLOT>& p, const uint32_t (&mk)[
   const int lane = lane_id();
   bool clash = false;
   const int half = N >> 1;
-  const int full = (N - 1) >> 1;   // distances taken from both ends' lower atom: all of 1 .. (N-1)/2
+  const int full = (N - 1) >> 1;   // every d in 1 .. full from each atom; for even N also d = N/2 from the lower end
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     if (s * 64 >= N) break;
     const int i = s * 64 + lane;
     if (i < N) {
-      int j = i;
-      for (int d = 1; d <= full; ++d) {
-        j = j + 1 == N ? 0 : j + 1;
-        const float4 pj = pos[j];
-        const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
-        if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2)
-          clash |= pair_changes(mk[s], __float_as_uint(pj.w), i, j, tors);
+      const float4* pi = pos + i;
+      const float xi = p.x[0][s], yi = p.x[1][s], zi = p.x[2][s];
+      auto near = [&](const float4& pj) {
+        const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+        return fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2;
+      };
+      auto rule = [&](int d, const float4& pj) {
+        const int j = i + d >= N ? i + d - N : i + d;
+        clash |= pair_changes(mk[s], __float_as_uint(pj.w), i, j, tors);
+      };
+      auto test = [&](int d) {
+        const float4 pj = pi[d];
+        const bool n0 = near(pj);
+        if (__ballot(n0) != 0ull && n0) rule(d, pj);
+      };
+      int d = 1;
+      for (; d + 3 <= full; d += 4) {   // four reads in flight, one vote for the rare bond rule
+        const float4 p0 = pi[d], p1 = pi[d + 1], p2 = pi[d + 2], p3 = pi[d + 3];
+        const bool n0 = near(p0), n1 = near(p1), n2 = near(p2), n3 = near(p3);
+        if (__ballot(n0 || n1 || n2 || n3) != 0ull) {
+          if (n0) rule(d, p0);
+          if (n1) rule(d + 1, p1);
+          if (n2) rule(d + 2, p2);
+          if (n3) rule(d + 3, p3);
+        }
       }
-      if (half > full && i < half) {   // even N: the opposite atom, from the lower end only
-        j = i + half;
-        const float4 pj = pos[j];
-        const float dx = p.x[0][s] - pj.x, dy = p.x[1][s] - pj.y, dz = p.x[2][s] - pj.z;
-        if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2)
-          clash |= pair_changes(mk[s], __float_as_uint(pj.w), i, j, tors);
-      }
+      for (; d <= full; ++d) test(d);
+      if (half > full && i < half) test(half);
     }
   }
   return !wave_any(clash);
@@ -302,28 +316,37 @@ __device__ bool move_clash_free(const MoveState<NSLOT>& p, const uint32_t (&mk)[
 
 template <int NSLOT>
 __device__ __forceinline__ void store_pose(float4* pos, const MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT],
-                                           int N) {
+                                           int N, bool wrap = false) {
   const int lane = lane_id();
+  const int full = (N - 1) >> 1;
 #pragma unroll
-  for (int s = 0; s < NSLOT; ++s)
-    if (s * 64 + lane < N) pos[s * 64 + lane] = make_float4(p.x[0][s], p.x[1][s], p.x[2][s], __uint_as_float(mk[s]));
+  for (int s = 0; s < NSLOT; ++s) {
+    const int a = s * 64 + lane;
+    const float4 v = make_float4(p.x[0][s], p.x[1][s], p.x[2][s], __uint_as_float(mk[s]));
+    if (a < N) pos[a] = v;
+    if (wrap && a < full) pos[N + a] = v;   // the copy the clash pass reads past atom N - 1
+  }
 }
 
-// LDS of one refinement wavefront in float4: pose, bond atoms, 1/lengths, bond
-// steps, bond gradients, gradient tile and results.
+// LDS of one refinement wavefront in float4: pose, gradient tile, bond atoms,
+// 1/lengths, bond steps, bond gradients, gradient results.  The clash pass's
+// copy of the first atoms runs from the pose into the tile's first 32 * nslot
+// float4; the torsion matrices sit in the tile after it.
 constexpr int refine_wave_float4(int nslot) { return 64 * nslot + 16 + 8 + 8 + 8 + GRAD_LDS_FLOAT4; }
+constexpr int refine_mats_float4(int nslot) { return 32 * nslot; }
+static_assert(refine_mats_float4(4) + 3 * 32 <= TILE_FLOATS / 4, "wrap copy and torsion matrices fit in the tile");
 
 template <int NSLOT>
 __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, RefineDev Rp, int n) {
   extern __shared__ float4 lds[];
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
   float4* pos = lds + (size_t)wave * refine_wave_float4(NSLOT);
-  int2* tors = reinterpret_cast<int2*>(pos + 64 * NSLOT);     // 32 entries (16 float4)
+  float* tile = reinterpret_cast<float*>(pos + 64 * NSLOT);   // column sums of the gradient; then wrap copy + matrices
+  int2* tors = reinterpret_cast<int2*>(tile + TILE_FLOATS);   // 32 entries (16 float4)
   float* inv_len = reinterpret_cast<float*>(tors + 32);       // 32 entries (8 float4)
   float* th = inv_len + 32;                                   // 32 bond steps (8 float4)
   float* thg = th + 32;                                       // 32 bond gradients (8 float4)
-  float* tile = thg + 32;                                     // column sums of the gradient; then the torsion matrices
-  float* res = tile + TILE_FLOATS;
+  float* res = thg + 32;                                      // gradient results
   const int w = blockIdx.x * nwaves + wave;   // pose: member w % kpl of the launch's ligand w / kpl
   if (w >= n) return;
   const int li = w / Rp.kpl, member = w - li * Rp.kpl;
@@ -401,7 +424,7 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
     }
     MoveState<NSLOT> cand = cur;
     if (table) {
-      float4* mats = reinterpret_cast<float4*>(tile);
+      float4* mats = reinterpret_cast<float4*>(tile) + refine_mats_float4(NSLOT);
       if (lane < K && thk != 0.f) {
         float c, sn, m[9];
         step_cos_sin(thk, c, sn);
@@ -417,7 +440,7 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
       apply_torsions(cand, mk, N, K, tors, inv_len, th);
     }
     apply_rigid(cand, q);
-    store_pose(pos, cand, mk, N);
+    store_pose(pos, cand, mk, N, true);
     wave_sync();
     const bool ok = move_clash_free(cand, mk, N, tors, pos, Rp.clash2);
     wave_sync();
