@@ -89,6 +89,39 @@ __device__ void apply_rigid(MoveState<NSLOT>& p, const float* q) {
   }
 }
 
+// The same rigid move with the three divisions of the axis done by lanes 0..2
+// at once (the same quotients; one division sequence instead of three).
+template <int NSLOT>
+__device__ void apply_rigid_lanes(MoveState<NSLOT>& p, const float* q) {
+  const float w2 = fmaf(q[5], q[5], fmaf(q[4], q[4], q[3] * q[3]));
+  if (w2 > 0.f) {
+    const float w = sqrtf(w2);
+    float c, s, m[9];
+    step_cos_sin(w, c, s);
+    const int lane = lane_id();
+    const float num = lane == 0 ? q[3] : (lane == 1 ? q[4] : q[5]);
+    const float u = num / w;
+    const float ux = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 0));
+    const float uy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 1));
+    const float uz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 2));
+    torsion_matrix(ux, uy, uz, c, s, m);
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      float y0, y1, y2;
+      mat_apply(m, p.x[0][sl] - p.piv[0], p.x[1][sl] - p.piv[1], p.x[2][sl] - p.piv[2], y0, y1, y2);
+      p.x[0][sl] = p.piv[0] + y0;
+      p.x[1][sl] = p.piv[1] + y1;
+      p.x[2][sl] = p.piv[2] + y2;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) p.x[d][sl] = p.x[d][sl] + q[d];
+    p.piv[d] = p.piv[d] + q[d];
+  }
+}
+
 // The local move: torsions deepest first, rotation about the pivot, translation.
 template <int NSLOT, bool LIB = false>
 __device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
@@ -137,20 +170,19 @@ __device__ __forceinline__ bool axes_fixed_under_torsions(const LigDev& P, int a
 // Torsions deepest first with matrices built beforehand: rows r of bond k at
 // mats[3k + r] = (m[3r], m[3r+1], m[3r+2], pivot coordinate r).  Valid when the
 // axes stay fixed under the torsions (axes_fixed_under_torsions).
+// mv: per slot, the bonds that rotate the lane's atom (bit k of the fragment
+// mask, cleared for b_k itself and for lanes past the last atom).
 template <int NSLOT>
-__device__ void apply_torsions_table(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K,
-                                     const int2* tors, const float* th, const float4* mats) {
-  const int lane = lane_id();
+__device__ void apply_torsions_table(MoveState<NSLOT>& p, const uint32_t (&mv)[NSLOT], int K, const float* th,
+                                     const float4* mats) {
   for (int k = K - 1; k >= 0; --k) {
     const float ang = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(th[k])));
     if (ang == 0.f) continue;
-    const int b = __builtin_amdgcn_readfirstlane(tors[k].y);
     const float4 r0 = mats[3 * k], r1 = mats[3 * k + 1], r2 = mats[3 * k + 2];
     const float m[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
 #pragma unroll
     for (int sl = 0; sl < NSLOT; ++sl) {
-      const int at = sl * 64 + lane;
-      if (at < N && ((mk[sl] >> k) & 1u) && at != b) {
+      if ((mv[sl] >> k) & 1u) {
         float y0, y1, y2;
         mat_apply(m, p.x[0][sl] - r0.w, p.x[1][sl] - r1.w, p.x[2][sl] - r2.w, y0, y1, y2);
         p.x[0][sl] = r0.w + y0;
@@ -362,6 +394,7 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
     inv_len[lane] = P.inv_len[toff + lane];
   }
   const bool table = axes_fixed_under_torsions(P, abase, toff, K);
+  uint32_t mv[NSLOT];   // bonds that rotate the lane's atom (b_k excluded)
   MoveState<NSLOT> cur, best;
   uint32_t mk[NSLOT];
 #pragma unroll
@@ -372,6 +405,13 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
     cur.x[1][s] = in ? P.y[cbase + a] : 0.f;
     cur.x[2][s] = in ? P.z[cbase + a] : 0.f;
     mk[s] = in ? P.mask[abase + a] : 0u;
+    mv[s] = mk[s];
+  }
+  for (int k = 0; k < K; ++k) {
+    const int b = __builtin_amdgcn_readfirstlane(P.tors_atoms[2 * (toff + k) + 1]);
+#pragma unroll
+    for (int s = 0; s < NSLOT; ++s)
+      if (s * 64 + lane == b) mv[s] &= ~(1u << k);
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) cur.piv[d] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.ref[3 * i + d])));
@@ -405,10 +445,17 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
     float dt[3], dw[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) { dt[d] = Rp.eta_t * g[d]; dw[d] = Rp.eta_w * g[3 + d]; }
-    const float nt = sqrtf(fmaf(dt[2], dt[2], fmaf(dt[1], dt[1], dt[0] * dt[0])));
-    const float nw = sqrtf(fmaf(dw[2], dw[2], fmaf(dw[1], dw[1], dw[0] * dw[0])));
-    const float ft = nt > Rp.clip_t ? Rp.clip_t / nt : 1.f;
-    const float fw = nw > Rp.clip_w ? Rp.clip_w / nw : 1.f;
+    // clip factors: lane 0 the translation's, lane 1 the rotation's
+    float ft, fw;
+    {
+      const bool rot = lane == 1;
+      const float a0 = rot ? dw[0] : dt[0], a1 = rot ? dw[1] : dt[1], a2 = rot ? dw[2] : dt[2];
+      const float clip = rot ? Rp.clip_w : Rp.clip_t;
+      const float nrm = sqrtf(fmaf(a2, a2, fmaf(a1, a1, a0 * a0)));
+      const float f = nrm > clip ? clip / nrm : 1.f;
+      ft = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f), 0));
+      fw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f), 1));
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       q[d] = (dt[d] * ft) * scale;
@@ -434,12 +481,12 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
         mats[3 * lane + 2] = make_float4(m[6], m[7], m[8], ax.za);
       }
       wave_sync();
-      apply_torsions_table(cand, mk, N, K, tors, th, mats);
+      apply_torsions_table(cand, mv, K, th, mats);
     } else {
       wave_sync();
       apply_torsions(cand, mk, N, K, tors, inv_len, th);
     }
-    apply_rigid(cand, q);
+    apply_rigid_lanes(cand, q);
     store_pose(pos, cand, mk, N, true);
     wave_sync();
     const bool ok = move_clash_free(cand, mk, N, tors, pos, Rp.clash2);
