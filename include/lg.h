@@ -206,7 +206,14 @@ typedef struct {
   const float* ref_point;          /* host [3n] */
 } lg_host_ligands;
 
-/* Host outputs of lg_dock_stream, in the lg_dock_out layout (pivot optional). */
+/* Host outputs of lg_dock_stream, in the lg_dock_out layout (pivot optional).
+ * chunk_done (optional, host [ceil(n / chunk)]) is a resume manifest: chunks
+ * whose entry is non-zero are skipped and their outputs left untouched; every
+ * other chunk gets entry 1 once its outputs have been written to the arrays
+ * above (the entry is stored after them).  With outputs and manifest in
+ * persistent memory (memory-mapped files), a screen interrupted part-way is
+ * completed by calling again with the same arrays; flushing them to storage
+ * is the caller's business. */
 typedef struct {
   float* score;                    /* host [n*top_k] */
   int32_t* restart_id;             /* host [n*top_k] */
@@ -214,6 +221,7 @@ typedef struct {
   float* y;
   float* z;
   float* pivot;                    /* host [n*top_k*3] or NULL */
+  int32_t* chunk_done;             /* host [ceil(n/chunk)] or NULL */
 } lg_host_out;
 
 /* Dock a library held in host memory, streamed through the device in chunks of

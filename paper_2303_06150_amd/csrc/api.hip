@@ -5,6 +5,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -704,6 +705,11 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     mx_tors = std::max(mx_tors, c.max_tors);
     chunks.push_back(c);
   }
+  // the chunks still to dock (a resume manifest marks finished ones)
+  std::vector<int> todo;
+  for (int ci = 0; ci < (int)chunks.size(); ++ci)
+    if (!O->chunk_done || O->chunk_done[ci] == 0) todo.push_back(ci);
+  if (todo.empty()) return LG_OK;
   // the workspace of the largest chunk, allocated before anything is in flight
   s = ensure_ws(p, dock_ws_layout(cap_n, P->restarts, P->sweeps, cap_tors,
                                   p->tuning.n_atom_clusters * p->tuning.n_rot_clusters).bytes);
@@ -758,9 +764,11 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     return fail(LG_ERR_OUT_OF_MEMORY, "stream buffers (2 x %zu bytes device and pinned host) could not be allocated", slot_bytes);
   }
 
-  // results of chunk c (in slot c % 2, copied back) into the caller's arrays
-  auto unpack = [&](const Chunk& c) {
-    const char* h = host[(&c - chunks.data()) % 2];
+  // results of the chunk at position t of todo (slot t % 2, copied back) into
+  // the caller's arrays, then its manifest entry
+  auto unpack = [&](int t) {
+    const Chunk& c = chunks[todo[t]];
+    const char* h = host[t % 2];
     const size_t nk = (size_t)(c.c1 - c.c0) * k;
     const size_t a0 = (size_t)H->atom_offset[c.c0], na = (size_t)H->atom_offset[c.c1] - a0;
     std::memcpy(O->score + (size_t)c.c0 * k, h + o_sc, nk * 4);
@@ -769,21 +777,25 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     std::memcpy(O->x + k * a0, h + o_ox, (size_t)k * na * 4);
     std::memcpy(O->y + k * a0, h + o_oy, (size_t)k * na * 4);
     std::memcpy(O->z + k * a0, h + o_oz, (size_t)k * na * 4);
+    if (O->chunk_done) {
+      std::atomic_thread_fence(std::memory_order_release);   // outputs before the entry
+      reinterpret_cast<volatile int32_t*>(O->chunk_done)[todo[t]] = 1;
+    }
   };
   auto copy = [&](void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t st) -> hipError_t {
     return bytes ? hipMemcpyAsync(dst, src, bytes, kind, st) : hipSuccess;
   };
 
-  const int nc = (int)chunks.size();
+  const int nc = (int)todo.size();
   for (int ci = 0; ci < nc && s == LG_OK; ++ci) {
-    const Chunk& c = chunks[ci];
+    const Chunk& c = chunks[todo[ci]];
     const int sl = ci % 2;
     char* h = host[sl];
     char* d = dev[sl];
     // the slot's previous chunk must be back on the host before its staging is reused
     if (ci >= 2) {
       if (hipEventSynchronize(ev_out[sl]) != hipSuccess) { s = fail(LG_ERR_DEVICE, "stream copy-back failed"); break; }
-      unpack(chunks[ci - 2]);
+      unpack(ci - 2);
     }
     // pack: offsets rebased to the chunk, arrays copied into pinned staging
     const int n = c.c1 - c.c0;
@@ -863,7 +875,7 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
       s = fail(LG_ERR_DEVICE, "stream copy-back failed");
       break;
     }
-    unpack(chunks[ci]);
+    unpack(ci);
   }
   release();
   return s;

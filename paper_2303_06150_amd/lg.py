@@ -75,7 +75,7 @@ class lg_host_ligands(ctypes.Structure):
 
 class lg_host_out(ctypes.Structure):
     _fields_ = [("score", c_void_p), ("restart_id", c_void_p), ("x", c_void_p), ("y", c_void_p),
-                ("z", c_void_p), ("pivot", c_void_p)]
+                ("z", c_void_p), ("pivot", c_void_p), ("chunk_done", c_void_p)]
 
 
 class lg_refine_params(ctypes.Structure):
@@ -350,10 +350,14 @@ def lg_dock_sites(pockets, ligs: DeviceLigands, restart_table, angle_table, *, s
 
 def lg_dock_stream(pocket: Pocket, atom_offset, tors_offset, x, y, z, frag_mask, tors_atoms, inv_bond_len,
                    ref_point, restart_table, angle_table, *, sweeps: int, top_k: int, trans_samples: int,
-                   trans_step: float, clash_dist2: float, chunk: int, want_pivot: bool = True, stream=None):
+                   trans_step: float, clash_dist2: float, chunk: int, want_pivot: bool = True, out=None,
+                   chunk_done=None, stream=None):
     """Dock a library held in host memory (numpy arrays), streamed through the
     device in chunks.  Returns numpy arrays: score [n,k], restart_id [n,k],
-    x/y/z [k*total_atoms], pivot [n,k,3] (if asked)."""
+    x/y/z [k*total_atoms], pivot [n,k,3] (if asked).  `out` may supply those
+    arrays (e.g. memory-mapped files); `chunk_done` (int32 [ceil(n/chunk)]) is
+    the resume manifest: chunks marked non-zero are skipped, the others marked
+    once their outputs are written."""
     arrs = [np.ascontiguousarray(atom_offset, np.int32), np.ascontiguousarray(tors_offset, np.int32),
             np.ascontiguousarray(x, np.float32), np.ascontiguousarray(y, np.float32),
             np.ascontiguousarray(z, np.float32), np.ascontiguousarray(frag_mask, np.uint32),
@@ -366,13 +370,25 @@ def lg_dock_stream(pocket: Pocket, atom_offset, tors_offset, x, y, z, frag_mask,
     R, A = int(restart_table.shape[0]), int(angle_table.shape[0])
     params = lg_dock_params(R, A, int(trans_samples), int(sweeps), int(top_k), LG_BUCKETED, float(trans_step),
                             float(clash_dist2), _ptr(restart_table), _ptr(angle_table))
-    out = dict(score=np.empty((n, top_k), np.float32), restart_id=np.empty((n, top_k), np.int32),
-               x=np.empty(top_k * ta, np.float32), y=np.empty(top_k * ta, np.float32),
-               z=np.empty(top_k * ta, np.float32))
-    if want_pivot:
-        out["pivot"] = np.empty((n, top_k, 3), np.float32)
-    O = lg_host_out(*[out[k_].ctypes.data_as(c_void_p) if k_ in out else None
-                      for k_ in ("score", "restart_id", "x", "y", "z", "pivot")])
+    if out is None:
+        out = dict(score=np.empty((n, top_k), np.float32), restart_id=np.empty((n, top_k), np.int32),
+                   x=np.empty(top_k * ta, np.float32), y=np.empty(top_k * ta, np.float32),
+                   z=np.empty(top_k * ta, np.float32))
+        if want_pivot:
+            out["pivot"] = np.empty((n, top_k, 3), np.float32)
+    shapes = dict(score=((n, top_k), np.float32), restart_id=((n, top_k), np.int32), x=((top_k * ta,), np.float32),
+                  y=((top_k * ta,), np.float32), z=((top_k * ta,), np.float32), pivot=((n, top_k, 3), np.float32))
+    for k_, a in out.items():
+        if k_ in shapes and (a.shape != shapes[k_][0] or a.dtype != shapes[k_][1] or not a.flags.c_contiguous):
+            raise ValueError(f"out[{k_!r}] must be a C-contiguous {np.dtype(shapes[k_][1])} array of shape "
+                             f"{shapes[k_][0]}")
+    if chunk_done is not None:
+        nch = -(-n // int(chunk)) if n else 0
+        if chunk_done.shape != (nch,) or chunk_done.dtype != np.int32 or not chunk_done.flags.c_contiguous:
+            raise ValueError(f"chunk_done must be a C-contiguous int32 array of shape ({nch},)")
+    ptrs = [out[k_].ctypes.data_as(c_void_p) if k_ in out else None
+            for k_ in ("score", "restart_id", "x", "y", "z", "pivot")]
+    O = lg_host_out(*ptrs, chunk_done.ctypes.data_as(c_void_p) if chunk_done is not None else None)
     _check(_lib.lg_dock_stream(pocket.handle, ctypes.byref(H), ctypes.byref(params), int(chunk), ctypes.byref(O),
                                _stream_handle(stream)))
     return out

@@ -65,6 +65,7 @@ def test_argument_checks_need_no_device():
     assert lib.lg_autotune(None, None, None, 1, None, None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_dock_stream(None, None, None, 1, None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_dock_sites(None, 1, None, None, None, 1, None) == lg.LG_ERR_INVALID_ARG
+    assert [f for f, _ in lg.lg_host_out._fields_][-1] == "chunk_done"
     handles = (ctypes.c_void_p * 1)()
     params = lg.lg_dock_params()
     outs = (lg.lg_dock_out * 1)()

@@ -59,3 +59,63 @@ def test_stream_rejects_bad_host_input():
                           top_k=2, trans_samples=16, trans_step=0.25, clash_dist2=oracle.CLASH2, chunk=2)
     assert e.value.status == lg.LG_ERR_INVALID_ARG
     pocket.free()
+
+
+def test_stream_resumes_from_manifest(tmp_path):
+    """Resume manifest: outputs and manifest as memory-mapped files.  A first
+    call with every chunk pending fills them and marks every chunk; a second
+    call that finds some chunks marked (as an interrupted screen would leave
+    them) docks only the others and leaves the marked chunks' outputs alone."""
+    import torch
+    from paper_2303_06150_amd import lg
+    lg.load_library()
+    w = gen.WORKLOADS["mixed"]
+    n, chunk = 2500, 400
+    L = gen.workload_ligands(w, np.arange(n, dtype=np.int64))
+    pk = gen.workload_pocket(w)
+    r32, _ = gen.restarts(w.restarts, w.seed)
+    a32, _ = gen.angles(w.angle_samples)
+    pocket = device_pocket(pk)
+    rt, at = torch.from_numpy(r32).cuda(), torch.from_numpy(a32).cuda()
+    T, k = w.angle_samples, w.top_k
+    kw = dict(sweeps=w.sweeps, top_k=k, trans_samples=T, trans_step=oracle.trans_step(T), clash_dist2=oracle.CLASH2)
+    ref = lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, **kw)
+    ta = int(L.atom_offset[-1])
+    nch = -(-n // chunk)
+
+    def files(tag, fill):
+        shapes = dict(score=((n, k), np.float32), restart_id=((n, k), np.int32), x=((k * ta,), np.float32),
+                      y=((k * ta,), np.float32), z=((k * ta,), np.float32), pivot=((n, k, 3), np.float32))
+        out = {}
+        for key, (shape, dt) in shapes.items():
+            out[key] = np.lib.format.open_memmap(tmp_path / f"{tag}_{key}.npy", mode="w+", dtype=dt, shape=shape)
+            out[key][...] = fill
+        done = np.lib.format.open_memmap(tmp_path / f"{tag}_done.npy", mode="w+", dtype=np.int32, shape=(nch,))
+        done[...] = 0
+        return out, done
+
+    say(f"stream resume: {n} ligands, {nch} chunks of {chunk}")
+    out, done = files("a", 0)
+    lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, out=out, chunk_done=done, **kw)
+    assert (done == 1).all()
+    for key in ref:
+        np.testing.assert_array_equal(out[key], ref[key], err_msg=key)
+    # an interrupted screen: chunks 0, 2, 3 and 6 finished, the rest not
+    out, done = files("b", -7)
+    finished = [0, 2, 3, 6]
+    done[finished] = 1
+    lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, out=out, chunk_done=done, **kw)
+    assert (done == 1).all()
+    for c in range(nch):
+        i0, i1 = c * chunk, min(n, (c + 1) * chunk)
+        a0, a1 = int(L.atom_offset[i0]), int(L.atom_offset[i1])
+        rows = dict(score=np.s_[i0:i1], restart_id=np.s_[i0:i1], pivot=np.s_[i0:i1],
+                    x=np.s_[k * a0:k * a1], y=np.s_[k * a0:k * a1], z=np.s_[k * a0:k * a1])
+        for key, sl in rows.items():
+            if c in finished:
+                assert (out[key][sl] == -7).all(), f"chunk {c} {key} was rewritten"
+            else:
+                np.testing.assert_array_equal(out[key][sl], ref[key][sl], err_msg=f"chunk {c} {key}")
+    # every chunk finished: nothing to do
+    lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, out=out, chunk_done=done, **kw)
+    pocket.free()
