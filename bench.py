@@ -279,6 +279,16 @@ def cpu_baseline(w, sample_ids, procs):
     return sum(done), wall, len(chunks)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _oracle_chunk(arg):
     name, ids = arg
     sys.path.insert(0, ROOT)
@@ -594,6 +604,13 @@ def main():
                    sample=f"{done} ligands of the {args.workload} workload (ids spread evenly over "
                           f"{w.n_ligands}), every restart ({w.restarts}), FP32 oracle, one process per core")
         log(f"cpu baseline: {done / wall:.2f} ligands/s on {used} processes")
+        # one core, measured (not divided out): 4 ligands spread over the library
+        one = np.linspace(0, w.n_ligands - 1, 4).astype(np.int64)
+        d1, wall1, _ = cpu_baseline(w, one, 1)
+        cpu["one_core"] = dict(value=round(d1 / wall1, 3), unit="ligands/s",
+                               sample=f"{d1} ligands (ids spread evenly), every restart, one process")
+        cpu["cpu_model"] = cpu_model()
+        log(f"cpu baseline, one core: {d1 / wall1:.3f} ligands/s ({cpu['cpu_model']})")
 
     buckets = [dict(bucket=b["bucket"], atoms_le=b["atom_bound"], slots=b["slots"], vgprs=b["vgprs"],
                     lds_bytes=b["lds_bytes"], blocks_per_cu=b["blocks_per_cu"], waves_in_flight=b["blocks"] * b["waves_per_block"],

@@ -247,7 +247,8 @@ lg_status lg_dock_stream(lg_pocket pocket, const lg_host_ligands* ligands, const
  * u_k . sum_{F_k} (x - x_{a_k}) x g with g the trilinear gradient and u_k the
  * unit bond axis.  moves (optional, trilinear only, same layout as grad): each
  * pose is first moved by its local parameters q = (t, omega, theta) --
- * torsions deepest first about the current bond axes, rotation by |omega| about
+ * torsions in reverse bond order (k = K-1 .. 0, deepest first when bonds are
+ * listed parents first) about the current bond axes, rotation by |omega| about
  * omega/|omega| through ref_point, translation (pivot included) -- then scored;
  * grad is then d(score)/dq at q (the omega part through the transposed left
  * Jacobian of SO(3)).  top_m > 0: top_idx / top_score (device [top_m]) receive

@@ -384,8 +384,9 @@ int dock_ligand(const og_grid* g, const og_ligand* l, const og_dock* d, double* 
 }
 
 // ---- refinement pose map (FP64 definition used for the adjoint check):
-// torsions deepest-first (k = K-1 .. 0) about the current bond axes, then a
-// rotation Exp(omega) about the pivot, then + t.
+// torsions in reverse bond order (k = K-1 .. 0; deepest first for parents-first
+// bond lists) about the current bond axes, then a rotation Exp(omega) about the
+// pivot, then + t.
 void rodrigues(const double u[3], double th, double m[9]) {
   double c = std::cos(th), s = std::sin(th), t = 1 - c;
   m[0] = c + t * u[0] * u[0];        m[1] = t * u[0] * u[1] - s * u[2]; m[2] = t * u[0] * u[2] + s * u[1];
@@ -422,7 +423,7 @@ void step_cos_sin(R x, R& c, R& s) {
   c = fma(x2, pc, (R)1);
 }
 
-// ---- local move (t, omega, theta) applied to a pose: torsions deepest first
+// ---- local move (t, omega, theta) applied to a pose: torsions in reverse bond order
 // (k = K-1 .. 0) about the current bond axes, then the rotation by |omega|
 // about the axis omega/|omega| through the pivot, then + t (the pivot moves
 // with t).  Every rotation uses the torsion-scan matrix script with the
@@ -727,7 +728,7 @@ extern "C" double oracle_pose_grad(const og_grid* gg, const og_ligand* l, const 
 }
 
 // Pose map of the local parameters q = (t[3], omega[3], theta[K]) applied to a
-// pose (xyz, pivot P): torsions deepest-first about the current bond axes,
+// pose (xyz, pivot P): torsions in reverse bond order about the current bond axes,
 // then Exp(omega) about P, then + t.  FP64.
 extern "C" int oracle_pose_map(const og_ligand* l, const double* xyz, const double* P, const double* q, double* out) {
   int N = l->N, K = l->K;

@@ -3,8 +3,8 @@
 RefineScore.apply(t, w, theta, pocket, poses) returns the trilinear score of
 every pose of `poses` after the local move (t [n,3] translation, w [n,3]
 axis-angle rotation about the pose's pivot, theta [total_torsions] bond angles,
-torsions applied deepest first).  Forward and backward are one lg_score call
-(moves + gradient); this module only packs and unpacks the parameter layout
+torsions applied in reverse bond order).  Forward and backward are one lg_score
+call (moves + gradient); this module only packs and unpacks the parameter layout
 and applies the chain rule's upstream factor.
 """
 from __future__ import annotations

@@ -4,7 +4,7 @@
 // One wavefront refines one pose; atom 64 s + lane sits in slot s.  Each step:
 // trilinear values and gradients per atom, force / torque / per-bond torque
 // sums in atom order (readlane), the clipped step, the local move (torsions
-// deepest first about the current bond axes, rotation about the pivot,
+// in reverse bond order about the current bond axes, rotation about the pivot,
 // translation), the intramolecular clash rule over every pair a torsion can
 // move, accept (keep the best pose) or reject (halve the step scale).  The
 // arithmetic is the CPU reference's FP32 script: sums in atom order, (cos, sin)
@@ -30,7 +30,8 @@ __device__ __forceinline__ void move_cos_sin(float x, float& c, float& s) {
   }
 }
 
-// Torsions deepest first, each about the bond axis at that moment.  th holds
+// Torsions in reverse bond order (k = K-1 .. 0; deepest first when bonds are
+// listed parents first), each about the bond axis at that moment.  th holds
 // the bond angles.
 template <int NSLOT, bool LIB = false>
 __device__ void apply_torsions(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
@@ -122,7 +123,7 @@ __device__ void apply_rigid_lanes(MoveState<NSLOT>& p, const float* q) {
   }
 }
 
-// The local move: torsions deepest first, rotation about the pivot, translation.
+// The local move: torsions in reverse bond order, rotation about the pivot, translation.
 template <int NSLOT, bool LIB = false>
 __device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
                            const float* inv_len, const float* q, const float* th) {
@@ -155,7 +156,7 @@ __device__ __forceinline__ LaneAxis lane_axis(const float4* pos, const int2* tor
 
 // Does a torsion ever move the axis atoms of a shallower bond?  When no bond j
 // moves a_k or b_k of a bond k < j (bonds listed parents first, as a preorder
-// numbering gives), every axis that the deepest-first sequence uses is the axis
+// numbering gives), every axis that the reverse-order sequence uses is the axis
 // at the start of the move, so all torsion matrices can be built at once.
 __device__ __forceinline__ bool axes_fixed_under_torsions(const LigDev& P, int abase, int toff, int K) {
   const int k = lane_id();
@@ -167,7 +168,7 @@ __device__ __forceinline__ bool axes_fixed_under_torsions(const LigDev& P, int a
   return !wave_any(moved);
 }
 
-// Torsions deepest first with matrices built beforehand: rows r of bond k at
+// Torsions in reverse bond order with matrices built beforehand: rows r of bond k at
 // mats[3k + r] = (m[3r], m[3r+1], m[3r+2], pivot coordinate r).  Valid when the
 // axes stay fixed under the torsions (axes_fixed_under_torsions).
 // mv: per slot, the bonds that rotate the lane's atom (bit k of the fragment
