@@ -290,7 +290,8 @@ __device__ float move_gradient(const GridDev& G, const MoveState<NSLOT>& p, cons
 // at pos[i + d].  Each unordered pair is visited once: the lane's atom i with
 // atom i + d for d = 1 .. N/2 (for even N the pair at d = N/2 only from its
 // lower end).  The distance test comes first; the bond rule is evaluated only
-// when some lane holds a pair inside the clash distance (bonded neighbours).
+// when some lane holds a pair inside the clash distance (bonded neighbours),
+// and the pass stops at the first clash, which already decides the step.
 __device__ __forceinline__ bool pair_changes(uint32_t mi, uint32_t mj, int i, int j, const int2* tors) {
   bool changes = false;
   for (uint32_t m = mi ^ mj; m != 0u && !changes; m &= m - 1u) {
@@ -311,7 +312,7 @@ __device__ bool move_clash_free(const MoveState<NSLOT>& p, const uint32_t (&mk)[
   const int full = (N - 1) >> 1;   // every d in 1 .. full from each atom; for even N also d = N/2 from the lower end
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
-    if (s * 64 >= N) break;
+    if (s * 64 >= N || wave_any(clash)) break;
     const int i = s * 64 + lane;
     if (i < N) {
       const float4* pi = pos + i;
@@ -338,10 +339,13 @@ __device__ bool move_clash_free(const MoveState<NSLOT>& p, const uint32_t (&mk)[
           if (n1) rule(d + 1, p1);
           if (n2) rule(d + 2, p2);
           if (n3) rule(d + 3, p3);
+          if (__ballot(clash) != 0ull) break;   // one clash decides: the step is rejected
         }
       }
-      for (; d <= full; ++d) test(d);
-      if (half > full && i < half) test(half);
+      if (__ballot(clash) == 0ull) {
+        for (; d <= full; ++d) test(d);
+        if (half > full && i < half) test(half);
+      }
     }
   }
   return !wave_any(clash);
