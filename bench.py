@@ -317,8 +317,9 @@ def main():
     ap.add_argument("--ablation-ligands", type=int, default=20000)
     ap.add_argument("--stream-chunk", type=int, default=25000,
                     help="side run: the library docked from host memory in chunks of this many ligands (0: skip)")
-    ap.add_argument("--autotune-ligands", type=int, default=4000,
-                    help="tune the bucketed path on this many ligands before timing (0: default tuning)")
+    ap.add_argument("--autotune-ligands", type=int, default=16000,
+                    help="tune the bucketed path on this many ligands before timing (0: default tuning); a "
+                         "small sample favours fewer buckets, whose second launch it cannot fill")
     ap.add_argument("--refine-ligands", type=int, default=20000,
                     help="side run: refine the top --refine-poses poses of this many ligands (0: skip)")
     ap.add_argument("--refine-poses", type=int, default=64)
