@@ -110,3 +110,22 @@ def test_sites_validation_and_handle_reuse(lgmod, tiny):
     assert len(pockets[0].bucket_stats()) > 0
     for p in pockets + [other]:
         p.free()
+
+
+def test_sites_single_site_and_empty_batch(lgmod, tiny):
+    """One site is lg_dock_batch; an empty batch docks nothing and succeeds."""
+    lg = lgmod
+    w, L = tiny["w"], tiny["ligs"]
+    pks = sites(32, 1, 9)
+    pockets = [device_pocket(p) for p in pks]
+    kw = dict(T=w.angle_samples, S=w.sweeps, top_k=w.top_k)
+    ref = dock_gpu(pockets[0], L, tiny["r32"], tiny["a32"], mode=lg.LG_BUCKETED, trace=False, **kw)
+    got = dock_sites(lg, pockets, L, tiny["r32"], tiny["a32"], site_major=True, **kw)[0]
+    for key in ref:
+        np.testing.assert_array_equal(got[key], ref[key], err_msg=key)
+    E = L.subset(np.arange(0))
+    assert E.n == 0
+    out = dock_sites(lg, pockets, E, tiny["r32"], tiny["a32"], site_major=False, **kw)
+    assert out[0]["score"].shape == (0, w.top_k)
+    for p in pockets:
+        p.free()
