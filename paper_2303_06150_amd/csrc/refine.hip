@@ -123,6 +123,30 @@ __device__ void apply_rigid_lanes(MoveState<NSLOT>& p, const float* q) {
   }
 }
 
+// The rigid move with its rotation matrix built beforehand (rows at M[0..2],
+// as apply_torsions_table's); rot: the rotation angle is non-zero.
+template <int NSLOT>
+__device__ void apply_rigid_table(MoveState<NSLOT>& p, const float* q, bool rot, const float4* M) {
+  if (rot) {
+    const float4 r0 = M[0], r1 = M[1], r2 = M[2];
+    const float m[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) {
+      float y0, y1, y2;
+      mat_apply(m, p.x[0][sl] - p.piv[0], p.x[1][sl] - p.piv[1], p.x[2][sl] - p.piv[2], y0, y1, y2);
+      p.x[0][sl] = p.piv[0] + y0;
+      p.x[1][sl] = p.piv[1] + y1;
+      p.x[2][sl] = p.piv[2] + y2;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl) p.x[d][sl] = p.x[d][sl] + q[d];
+    p.piv[d] = p.piv[d] + q[d];
+  }
+}
+
 // The local move: torsions in reverse bond order, rotation about the pivot, translation.
 template <int NSLOT, bool LIB = false>
 __device__ void apply_move(MoveState<NSLOT>& p, const uint32_t (&mk)[NSLOT], int N, int K, const int2* tors,
@@ -371,7 +395,7 @@ __device__ __forceinline__ void store_pose(float4* pos, const MoveState<NSLOT>& 
 // float4; the torsion matrices sit in the tile after it.
 constexpr int refine_wave_float4(int nslot) { return 64 * nslot + 16 + 8 + 8 + 8 + GRAD_LDS_FLOAT4; }
 constexpr int refine_mats_float4(int nslot) { return 32 * nslot; }
-static_assert(refine_mats_float4(4) + 3 * 32 <= TILE_FLOATS / 4, "wrap copy and torsion matrices fit in the tile");
+static_assert(refine_mats_float4(4) + 3 * 33 <= TILE_FLOATS / 4, "wrap copy and the matrices fit in the tile");
 
 template <int NSLOT>
 __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, RefineDev Rp, int n) {
@@ -476,22 +500,39 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
     }
     MoveState<NSLOT> cand = cur;
     if (table) {
+      // every matrix of the move in one pass: lane k < K bond k's, lane K the
+      // rigid rotation's (axis w/|w| from three quotients by lanes 0..2)
       float4* mats = reinterpret_cast<float4*>(tile) + refine_mats_float4(NSLOT);
-      if (lane < K && thk != 0.f) {
+      const float w2 = fmaf(q[5], q[5], fmaf(q[4], q[4], q[3] * q[3]));
+      const bool rot = w2 > 0.f;
+      float w = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+      if (rot) {
+        w = sqrtf(w2);
+        const float num = lane == 0 ? q[3] : (lane == 1 ? q[4] : q[5]);
+        const float u = num / w;
+        wx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 0));
+        wy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 1));
+        wz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 2));
+      }
+      const bool bond = lane < K && thk != 0.f;
+      if (bond || (lane == K && rot)) {
+        const float ang = bond ? thk : w;
+        const float ux = bond ? ax.ux : wx, uy = bond ? ax.uy : wy, uz = bond ? ax.uz : wz;
         float c, sn, m[9];
-        step_cos_sin(thk, c, sn);
-        torsion_matrix(ax.ux, ax.uy, ax.uz, c, sn, m);
+        step_cos_sin(ang, c, sn);
+        torsion_matrix(ux, uy, uz, c, sn, m);
         mats[3 * lane] = make_float4(m[0], m[1], m[2], ax.xa);
         mats[3 * lane + 1] = make_float4(m[3], m[4], m[5], ax.ya);
         mats[3 * lane + 2] = make_float4(m[6], m[7], m[8], ax.za);
       }
       wave_sync();
       apply_torsions_table(cand, mv, K, th, mats);
+      apply_rigid_table(cand, q, rot, mats + 3 * K);
     } else {
       wave_sync();
       apply_torsions(cand, mk, N, K, tors, inv_len, th);
+      apply_rigid_lanes(cand, q);
     }
-    apply_rigid_lanes(cand, q);
     store_pose(pos, cand, mk, N, true);
     wave_sync();
     const bool ok = move_clash_free(cand, mk, N, tors, pos, Rp.clash2);
