@@ -581,7 +581,7 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
     if (e == hipSuccess) e = hipEventRecord(fork, cs);
     for (size_t l = 0; l < nl && e == hipSuccess; ++l) {
       const lg_bucket_stat& b = launches[l];
-      hipStream_t bs = l == 0 ? cs : p->branches[(l - 1) % p->branches.size()];
+      hipStream_t bs = (l == 0 || p->branches.empty()) ? cs : p->branches[(l - 1) % p->branches.size()];
       if (l > 0) e = hipStreamWaitEvent(bs, fork, 0);
       if (e == hipSuccess && timed) e = hipEventRecord(p->events[1 + 2 * l], bs);
       lg::QueueDev Q{perm, start, cursors, b.bucket, tu.restart_chunk};
