@@ -499,10 +499,13 @@ def main():
     # HBM bytes of one step's bucket launches (all buckets), measured on this source
     traffic = read_traffic(f"dock_buckets_{args.workload}")
     achieved = dom_ops / (dom_ms * 1e-3)
+    # the sustained non-packed v_fma_f32 rate on this device, beside the derived peak
+    valu_meas = lg.lg_valu_probe(pocket, 0)
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(PEAK_LANE_OPS / 1e12, 3),
                     unit="TOP/s", frac=round(achieved / PEAK_LANE_OPS, 4), traffic=traffic, kernel=kernel,
                     kernel_ms=round(dom_ms, 3), ligands_in_launch=int(sum(b["ligands"] for b in busy)),
-                    algorithmic_ops_per_launch=dom_ops)
+                    algorithmic_ops_per_launch=dom_ops, measured_valu_peak=round(valu_meas / 1e12, 3),
+                    frac_of_measured_peak=round(achieved / valu_meas, 4))
     total_ops = float(ops.sum())
 
     # ---- side runs: plain per-ligand launches, single-bucket ablation

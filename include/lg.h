@@ -366,6 +366,15 @@ int32_t lg_bucket_stats(lg_pocket pocket, lg_bucket_stat* out, int32_t capacity)
  * units, t the threads per block and ws the wavefront size.  Host only. */
 int64_t lg_bucket_size(int64_t blocks_per_unit, int64_t units, int64_t threads_per_block, int64_t wave_size);
 
+/* Measurement aid for the ALU roofline of the kernels above: the sustained
+ * rate, in lane-operations per second, of one non-packed VALU operation on the
+ * handle's device -- eight independent chains per lane, eight wavefronts per
+ * SIMD, `iters` iterations, timed with events on `stream` after one warm-up
+ * launch.  kind: 0 v_fma_f32, 1 v_add_f32, 2 v_add_u32, 3 v_med3_f32,
+ * 4 v_mad_i32_i24.  Allocates and frees a small buffer; synchronises
+ * `stream`. */
+lg_status lg_valu_probe(lg_pocket pocket, int32_t kind, int32_t iters, double* lane_ops_per_s, void* stream);
+
 /* Cluster boundaries (Sec. 3): atom clusters at multiples of the wavefront
  * size (n_clusters-1 boundaries ws, 2ws, ..., the last cluster takes the
  * rest up to max_atoms); rotamer clusters split [0, max_rot] unevenly, finer at

@@ -22,6 +22,7 @@ hipError_t launch_dock_plain(int nslot, int spl, int wpb, const GridDev& G, cons
 hipError_t launch_dock_bucket(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
                               const DockDev& D, const QueueDev& Q, hipStream_t st);
 hipError_t occupancy_dock_bucket(int nslot, int spl, int wpb, int tab_len, int* blocks_per_cu);
+hipError_t launch_valu_probe(int kind, int blocks, int iters, float* out, hipStream_t st);
 hipError_t launch_dock_sites(int nslot, int spl, int wpb, int blocks, const GridDev& G, const LigDev& Lg,
                              const DockDev& D, const QueueDev& Q, const SitesDev& Sd, hipStream_t st);
 hipError_t attributes_dock_bucket(int nslot, int spl, hipFuncAttributes* attr);
@@ -1324,6 +1325,36 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
     R.lig_ids = perm + hs[c];
     LG_HIP(lg::launch_refine(c + 1, p->grid, lig_dev(L), R, cnt * kpl, st));
   }
+  return LG_OK;
+}
+
+lg_status lg_valu_probe(lg_pocket p, int32_t kind, int32_t iters, double* lane_ops_per_s, void* stream) {
+  if (!p || !lane_ops_per_s) return fail(LG_ERR_INVALID_ARG, "pocket and lane_ops_per_s must not be NULL");
+  if (kind < 0 || kind > 4) return fail(LG_ERR_INVALID_ARG, "kind %d outside 0..4", kind);
+  if (iters < 1 || iters > 1000000) return fail(LG_ERR_LIMIT, "iters %d outside 1..1000000", iters);
+  hipStream_t st = (hipStream_t)stream;
+  LG_HIP(hipSetDevice(p->device));
+  const int blocks = p->cus * 8;   // eight 4-wavefront blocks per CU: eight wavefronts per SIMD
+  float* out = nullptr;
+  if (hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LG_ERR_OUT_OF_MEMORY, "probe buffer could not be allocated");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.f;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = lg::launch_valu_probe(kind, blocks, iters, out, st);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = lg::launch_valu_probe(kind, blocks, iters, out, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (e != hipSuccess) return fail(LG_ERR_DEVICE, "probe failed: %s", hipGetErrorString(e));
+  *lane_ops_per_s = 8.0 * iters * (double)blocks * 256.0 / (ms * 1e-3);
   return LG_OK;
 }
 

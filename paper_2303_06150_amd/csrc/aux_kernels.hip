@@ -266,4 +266,45 @@ hipError_t launch_check(const int32_t* atom_offset, const int32_t* tors_offset, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- VALU rate probe
+// Eight independent chains of one non-packed VALU operation per lane, no memory
+// traffic but one store per lane: the sustained issue rate of that operation.
+template <int KIND>
+__global__ __launch_bounds__(256) void valu_probe_kernel(float* out, int iters, float a, float b) {
+  float x[8];
+  int y[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    x[i] = threadIdx.x * 0.001f + i;
+    y[i] = threadIdx.x + i;
+  }
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if (KIND == 0) x[i] = fmaf(x[i], a, b);                      // v_fma_f32
+      if (KIND == 1) x[i] = x[i] + a;                              // v_add_f32
+      if (KIND == 2) y[i] = y[i] + it;                             // v_add_u32
+      if (KIND == 3) x[i] = __builtin_amdgcn_fmed3f(x[i], a, b);   // v_med3_f32
+      if (KIND == 4) y[i] = __mul24(y[i], 3) + it;                 // v_mad_i32_i24
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s += x[i] + (float)y[i];
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+hipError_t launch_valu_probe(int kind, int blocks, int iters, float* out, hipStream_t st) {
+  const dim3 grid(blocks), block(256);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(valu_probe_kernel<0>, grid, block, 0, st, out, iters, 1.0001f, 0.5f); break;
+    case 1: hipLaunchKernelGGL(valu_probe_kernel<1>, grid, block, 0, st, out, iters, 1.0001f, 0.5f); break;
+    case 2: hipLaunchKernelGGL(valu_probe_kernel<2>, grid, block, 0, st, out, iters, 1.0001f, 0.5f); break;
+    case 3: hipLaunchKernelGGL(valu_probe_kernel<3>, grid, block, 0, st, out, iters, 0.1f, 0.5f); break;
+    case 4: hipLaunchKernelGGL(valu_probe_kernel<4>, grid, block, 0, st, out, iters, 0.1f, 0.5f); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace lg

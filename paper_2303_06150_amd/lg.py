@@ -26,7 +26,7 @@ LG_PLAIN, LG_BUCKETED = 0, 1
 LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
 
 EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_sites", "lg_dock_stream", "lg_score",
-           "lg_refine", "lg_rank", "lg_autotune",
+           "lg_refine", "lg_rank", "lg_autotune", "lg_valu_probe",
            "lg_set_tuning", "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
            "lg_last_error", "lg_version")
 
@@ -125,6 +125,7 @@ def load_library(path: str = LIB_PATH):
     lib.lg_rank.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.lg_autotune.argtypes = [c_void_p, P(lg_ligands), P(lg_dock_params), c_int32, P(lg_tuning),
                                 P(c_float), c_void_p]
+    lib.lg_valu_probe.argtypes = [c_void_p, c_int32, c_int32, P(ctypes.c_double), c_void_p]
     lib.lg_set_tuning.argtypes = [c_void_p, P(lg_tuning)]
     lib.lg_get_tuning.argtypes = [c_void_p, P(lg_tuning)]
     lib.lg_bucket_stats.argtypes = [c_void_p, P(lg_bucket_stat), c_int32]
@@ -135,7 +136,7 @@ def load_library(path: str = LIB_PATH):
     lib.lg_rotamer_clusters.argtypes = [c_int32, c_int32, P(c_int32)]
     lib.lg_last_error.restype = ctypes.c_char_p
     for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_sites", "lg_dock_stream", "lg_score",
-                 "lg_refine", "lg_rank", "lg_autotune", "lg_set_tuning", "lg_get_tuning"):
+                 "lg_refine", "lg_rank", "lg_autotune", "lg_valu_probe", "lg_set_tuning", "lg_get_tuning"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -449,6 +450,17 @@ def refine_params(steps=50, eta_t=1e-2, eta_w=1e-3, eta_th=1e-3, clip_t=0.1, cli
                   clash_dist2=4.84, poses_per_ligand=1) -> lg_refine_params:
     return lg_refine_params(int(steps), eta_t, eta_w, eta_th, clip_t, clip_w, clip_th, clash_dist2,
                             int(poses_per_ligand))
+
+
+VALU_PROBE_KINDS = ("v_fma_f32", "v_add_f32", "v_add_u32", "v_med3_f32", "v_mad_i32_i24")
+
+
+def lg_valu_probe(pocket: Pocket, kind: int = 0, iters: int = 200000, stream=None) -> float:
+    """Sustained lane-operations per second of one non-packed VALU operation
+    (VALU_PROBE_KINDS[kind]) on the pocket's device."""
+    r = ctypes.c_double(0.0)
+    _check(_lib.lg_valu_probe(pocket.handle, int(kind), int(iters), ctypes.byref(r), _stream_handle(stream)))
+    return float(r.value)
 
 
 def lg_rank(pocket: Pocket, score, group_size: int, top_m: int, stream=None):

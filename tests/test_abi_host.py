@@ -74,6 +74,7 @@ def test_argument_checks_need_no_device():
     assert lib.lg_dock_sites(handles, 1, None, ctypes.byref(params), outs, 1, None) == lg.LG_ERR_INVALID_ARG
     assert "pocket 0 is NULL" in lg.lg_last_error()
     assert lib.lg_set_tuning(None, None) == lg.LG_ERR_INVALID_ARG
+    assert lib.lg_valu_probe(None, 0, 1, None, None) == lg.LG_ERR_INVALID_ARG
     assert lib.lg_free_pocket(None) == lg.LG_OK
     desc = lg.lg_pocket_desc(1, 32, 32, 0.5, 2.0, (ctypes.c_float * 3)(), (ctypes.c_float * 3)(), 0.0)
     h = ctypes.c_void_p()

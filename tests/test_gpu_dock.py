@@ -493,3 +493,18 @@ def test_bench_configuration_full_library(lgmod):
     i = int(rng.integers(L.n))
     ref = dock_oracle(pk, L, i, r32, a32, T=T, S=w.sweeps)
     compare_ligand(h, L, i, ref, np.arange(w.restarts), k, w.restarts, "bench configuration, all restarts")
+
+
+def test_valu_probe_is_below_the_derived_peak(lgmod, tiny):
+    """The probe's sustained rates (the roofline's measured context) are
+    positive and never above 256 CUs x 64 lanes x 2.4 GHz / 4 cycles."""
+    lg = lgmod
+    pocket = device_pocket(tiny["pocket"])
+    derived = 256 * 4 * 16 * 2.4e9
+    for kind, name in enumerate(lg.VALU_PROBE_KINDS):
+        r = lg.lg_valu_probe(pocket, kind, 20000)
+        say(f"valu probe {name}: {r / 1e12:.2f} T lane-op/s")
+        assert 0.5 * derived < r < 1.02 * derived, (name, r)
+    with pytest.raises(lg.LgError):
+        lg.lg_valu_probe(pocket, 9, 10)
+    pocket.free()
