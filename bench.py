@@ -606,7 +606,8 @@ def main():
                                   roofline=dict(bound="alu", achieved=round(rach / 1e12, 3),
                                                 peak=round(PEAK_LANE_OPS / 1e12, 3), unit="TOP/s",
                                                 frac=round(rach / PEAK_LANE_OPS, 4), kernel="refine_kernel<s>",
-                                                algorithmic_ops=rops))
+                                                algorithmic_ops=rops,
+                                                measured_valu_peak=round(lg.lg_valu_probe(pocket, 0) / 1e12, 3)))
             if not args.no_cpu_baseline:
                 import oracle
                 hx, hy, hz = (od[c].cpu().numpy() for c in ("x", "y", "z"))
