@@ -39,6 +39,8 @@ struct SampleReg {
   uint32_t valid_a, valid_t;   // bit q: sample lane + 64 q exists
   bool half_turn;              // A = 64 SPL and sample j + A/2 is sample j turned by pi:
                                // (cos, sin) of the two are exact negatives
+  bool quarter_turn;           // A = 64 SPL and samples j + A/4, j + A/2, j + 3A/4 are j
+                               // turned by pi/2, pi, 3pi/2: (-s, c), (-c, -s), (s, -c) exactly
 };
 
 
@@ -230,7 +232,33 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
       out[q + SPL / 2] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
     }
   };
-  if (SPL % 2 == 0 && sm.half_turn)
+  // samples j + A/4 and j + 3A/4 in the same way: with (cos, sin) = (-s, c) the
+  // rotated offsets are (-nq, np), with (s, -c) they are (nq, -np), exactly
+  auto gather_quarter_turn = [&](int t, float (&out)[SPL]) {
+    const float4 d = scr[t];
+    const int part = __float_as_int(d.z);
+    constexpr int Q4 = SPL / 4;
+#pragma unroll
+    for (int q = 0; q < Q4; ++q) {
+      const float np = fmaf(sm.c[q], d.x, -(sm.s[q] * d.y));
+      const float nq = fmaf(sm.s[q], d.x, sm.c[q] * d.y);
+      int ip = clamp_node(fmaf(pP + np, ih, cP), fnP);
+      int iq = clamp_node(fmaf(pQ + nq, ih, cQ), fnQ);
+      out[q] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+      ip = clamp_node(fmaf(pP - nq, ih, cP), fnP);
+      iq = clamp_node(fmaf(pQ + np, ih, cQ), fnQ);
+      out[q + Q4] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+      ip = clamp_node(fmaf(pP - np, ih, cP), fnP);
+      iq = clamp_node(fmaf(pQ - nq, ih, cQ), fnQ);
+      out[q + 2 * Q4] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+      ip = clamp_node(fmaf(pP + nq, ih, cP), fnP);
+      iq = clamp_node(fmaf(pQ - np, ih, cQ), fnQ);
+      out[q + 3 * Q4] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+    }
+  };
+  if (SPL % 4 == 0 && sm.quarter_turn)
+    pipelined_sum<SPL>(N, gather_quarter_turn, acc);
+  else if (SPL % 2 == 0 && sm.half_turn)
     pipelined_sum<SPL>(N, gather_half_turn, acc);
   else
     pipelined_sum<SPL>(N, gather, acc);
@@ -447,6 +475,7 @@ __device__ void load_samples(const DockDev& D, SampleReg<SPL>& sm) {
   sm.valid_a = 0u;
   sm.valid_t = 0u;
   sm.half_turn = false;
+  sm.quarter_turn = false;
 #pragma unroll
   for (int q = 0; q < SPL; ++q) {
     const int j = lane + 64 * q;
@@ -472,6 +501,15 @@ __device__ void load_samples(const DockDev& D, SampleReg<SPL>& sm) {
     for (int q = 0; q < SPL / 2; ++q)
       pair = pair && sm.c[q + SPL / 2] == -sm.c[q] && sm.s[q + SPL / 2] == -sm.s[q];
     sm.half_turn = !wave_any(!pair);
+  }
+  if (SPL % 4 == 0 && D.A == 64 * SPL) {
+    constexpr int Q4 = SPL / 4;
+    bool quad = true;
+#pragma unroll
+    for (int q = 0; q < Q4; ++q)
+      quad = quad && sm.c[q + Q4] == -sm.s[q] && sm.s[q + Q4] == sm.c[q] && sm.c[q + 2 * Q4] == -sm.c[q] &&
+             sm.s[q + 2 * Q4] == -sm.s[q] && sm.c[q + 3 * Q4] == sm.s[q] && sm.s[q + 3 * Q4] == -sm.c[q];
+    sm.quarter_turn = !wave_any(!quad);
   }
 }
 

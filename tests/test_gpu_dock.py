@@ -47,7 +47,7 @@ def ragged_ligands():
     return gen.ligands_from_sizes(ids, 11, np.array(N), np.array(K))
 
 
-@pytest.mark.parametrize("A,T", [(48, 40), (130, 64), (256, 256)])
+@pytest.mark.parametrize("A,T", [(48, 40), (130, 64), (256, 256), (512, 128)])
 def test_ragged_sizes_and_sample_counts(lgmod, tiny, A, T):
     lg = lgmod
     pk = gen.pocket(48, 0.5, 60, 400, 3)
