@@ -4,9 +4,10 @@
  * The calls follow the paper's statement of the virtual-screening problem
  * (Sec. 2): identify a docking site (lg_load_pocket), dock every ligand of a
  * bucket into it, i.e. estimate the 3D placement of its atoms
- * (lg_dock_batch; lg_dock_stream for a library held in host memory),
- * evaluate the interaction strength (lg_score), refine the best poses locally
- * (lg_refine) and rank the library (lg_rank).  Buckets of ligands of similar
+ * (lg_dock_batch; lg_dock_stream for a library held in host memory,
+ * lg_dock_sites for several docking sites of one target), evaluate the
+ * interaction strength (lg_score), refine the best poses locally (lg_refine)
+ * and rank the library (lg_rank).  Buckets of ligands of similar
  * atom and rotamer counts, each docked by a kernel instantiated for its size
  * class with a bucket size derived from occupancy, are the paper's
  * out-of-kernel optimisation (Sec. 3, Eq. 1); lg_dock_batch with LG_BUCKETED is
@@ -21,8 +22,9 @@
  *  - Every call returns an lg_status; nothing throws across the ABI and
  *    nothing aborts.  Argument and limit checks are synchronous and return
  *    before any work is enqueued (device-resident ligand data is checked by a
- *    small kernel whose counters are read back before the docking work).  HIP errors map to LG_ERR_DEVICE and are
- *    reported by the call that observes them.  lg_last_error() gives a
+ *    small kernel whose counters are read back before the docking work).
+ *    HIP errors map to LG_ERR_DEVICE and are reported by the call that
+ *    observes them.  lg_last_error() gives a
  *    message for the last failing call of the calling thread.
  *  - Coordinates are Angstrom, FP32.  Arithmetic is FP32 with explicit fma
  *    (no contraction); given the same inputs, results are bitwise
