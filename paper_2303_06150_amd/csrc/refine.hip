@@ -457,10 +457,12 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   // so its gradient is reused); pending: cur was accepted and not yet compared
   // with the best -- the gradient pass's column 0 is its score
   bool fresh = true, pending = false;
+  // pos holds cur whenever a gradient is due: here, and after an accepted step
+  // (the candidate was stored for its clash pass)
+  store_pose(pos, cur, mk, N);
+  wave_sync();
   for (int step = 0; step < Rp.steps; ++step) {
     if (fresh) {
-      store_pose(pos, cur, mk, N);
-      wave_sync();
       ax = lane_axis(pos, tors, inv_len, K);
       const float sc = move_gradient(G, cur, mk, N, K, tors, pos, ax, g, thg, tile, res);
       wave_sync();
