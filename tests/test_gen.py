@@ -95,3 +95,19 @@ def test_tables():
         np.testing.assert_allclose(M @ M.T, np.eye(3), atol=1e-12)
         assert abs(np.linalg.det(M) - 1) < 1e-12
         assert np.linalg.norm(r[9:]) <= 2.0
+
+
+def test_angle_table_turn_symmetries():
+    """The generated (cos, sin) table is exactly symmetric under quarter and half
+    turns at every A that is a multiple of 4: sample j + A/4 holds (-s_j, c_j),
+    j + A/2 holds (-c_j, -s_j), j + 3A/4 holds (s_j, -c_j).  The docking kernel
+    checks this at start and then rotates once per four samples."""
+    for A in (4, 64, 128, 256, 512, 1024):
+        a, _ = gen.angles(A)
+        c, s = a[:, 0], a[:, 1]
+        q = A // 4
+        j = np.arange(q)
+        assert np.array_equal(c[j + q], -s[j]) and np.array_equal(s[j + q], c[j]), A
+        assert np.array_equal(c[j + 2 * q], -c[j]) and np.array_equal(s[j + 2 * q], -s[j]), A
+        assert np.array_equal(c[j + 3 * q], s[j]) and np.array_equal(s[j + 3 * q], -c[j]), A
+        assert c[0] == 1.0 and s[0] == 0.0
