@@ -21,8 +21,11 @@
  *    asynchronous: keep buffers alive until the stream has completed.
  *  - Every call returns an lg_status; nothing throws across the ABI and
  *    nothing aborts.  Argument and limit checks are synchronous and return
- *    before any work is enqueued (device-resident ligand data is checked by a
- *    small kernel whose counters are read back before the docking work).
+ *    before any work is enqueued.  Ligand data is checked on the host when the
+ *    batch carries host copies of its offsets and bond atoms (lg_ligands), and
+ *    the call then enqueues without waiting on the stream; otherwise a small
+ *    kernel checks the device copies and its counters are read back before the
+ *    docking work (one stream synchronisation).
  *    HIP errors map to LG_ERR_DEVICE and are reported by the call that
  *    observes them.  lg_last_error() gives a
  *    message for the last failing call of the calling thread.
@@ -82,15 +85,20 @@ typedef struct lg_pocket_s* lg_pocket;
  *   n                 number of ligands (0 is allowed: nothing to do)
  *   total_atoms       host value = atom_offset[n]
  *   total_torsions    host value = tors_offset[n]
- *   atom_offset_host  optional host copies of the offsets, checked on the host
- *   tors_offset_host  before any launch (sizes, limits, totals).  Every call also
+ *   atom_offset_host  optional host copies of the offsets and of the bond atoms,
+ *   tors_offset_host  each checked on the host before any launch (sizes, limits,
+ *   tors_atoms_host   totals, bond ids).  They must equal the device arrays.
+ *                     With all three, lg_dock_batch, lg_score and lg_refine
+ *                     take the batch's sizes from them and do not read device
+ *                     data back (lg_dock_batch and lg_score then return without
+ *                     waiting on the stream).  Without all three, the call
  *                     checks the device copies with one small kernel and a
  *                     synchronous read-back of its counters (sizes, limits,
- *                     consistency, local ids), so bad device data is reported
+ *                     consistency, local ids).  Either way bad data is reported
  *                     as LG_ERR_INVALID_ARG / LG_ERR_LIMIT, never docked.
  * Limits: 1 <= atoms <= LG_MAX_ATOMS and 0 <= bonds <= LG_MAX_TORSIONS per
- * ligand; local ids in range; total_atoms <= 2^30 - 256 per batch (the
- * kernels address the atom arrays with 32-bit byte offsets). */
+ * ligand; a bond's two atoms are distinct local ids; total_atoms <= 2^30 - 256
+ * per batch (the kernels address the atom arrays with 32-bit byte offsets). */
 typedef struct {
   int32_t n;
   int32_t total_atoms;
@@ -106,6 +114,7 @@ typedef struct {
   const float* ref_point;          /* device [3n] rigid-body pivot P0 (e.g. the centroid) */
   const int32_t* atom_offset_host; /* host [n+1] or NULL */
   const int32_t* tors_offset_host; /* host [n+1] or NULL */
+  const int32_t* tors_atoms_host;  /* host [2*total_torsions] or NULL (needs the two above) */
 } lg_ligands;
 
 /* Docking parameters.  Per restart r the ligand is placed at
@@ -171,7 +180,9 @@ lg_status lg_free_pocket(lg_pocket pocket);
  * restart records its final score and the selected sample of each scan; the
  * kept poses are rebuilt from those records.  Workspace: 4 n R bytes of scores
  * plus 2 R sweeps (6 n + total_torsions) bytes of records, held by the pocket
- * handle: calls on one handle must not overlap. */
+ * handle (growing it waits for the device): calls on one handle must not
+ * overlap.  LG_BUCKETED needs n * ceil(R / restart_chunk) < 2^30 work items
+ * (else LG_ERR_LIMIT before any launch). */
 lg_status lg_dock_batch(lg_pocket pocket, const lg_ligands* ligands, const lg_dock_params* params,
                         const lg_dock_out* out, void* stream);
 
@@ -306,7 +317,7 @@ typedef struct {
   int32_t n_rot_clusters;         /* 1..32 */
   int32_t rot_bounds[32];         /* increasing, each 0..LG_MAX_TORSIONS */
   int32_t waves_per_block[4];     /* each 1, 2 or 4 */
-  int32_t restart_chunk;          /* >= 1 */
+  int32_t restart_chunk;          /* 1..LG_MAX_RESTARTS */
   int32_t grid_scale;             /* 1..64 */
   int32_t plain_waves_per_block;  /* 1, 2 or 4 */
   int32_t use_graph;              /* 1: capture once and replay as a HIP graph; 0: launch

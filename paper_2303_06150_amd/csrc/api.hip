@@ -2,7 +2,6 @@
 // per-ligand launch sequence, the bucketed persistent sequence captured as a
 // HIP graph, scoring and ranking.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <atomic>
@@ -30,10 +29,9 @@ hipError_t launch_topk(int nslot, const LigDev& Lg, const DockDev& D, int n, int
                        float* ox, float* oy, float* oz, float* all_scores, float* pivot, hipStream_t st);
 hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, float* score, float* grad,
                         hipStream_t st);
-hipError_t launch_rank_prep(const float* score, int n_groups, int group, float* keys, int32_t* vals,
-                            int32_t* member, hipStream_t st);
-hipError_t launch_rank_gather(const float* keys, const int32_t* vals, const int32_t* member, int m, int32_t* top_idx,
-                              float* top_score, int32_t* top_member, hipStream_t st);
+size_t rank_scratch_bytes(int n, int m);
+hipError_t launch_rank(const float* score, int n, int group, int m, void* scratch, int32_t* top_idx,
+                       float* top_score, int32_t* top_member, hipStream_t st);
 hipError_t launch_pad(const float* src, int nx, int ny, int nz, float out, float* dst, hipStream_t st);
 hipError_t launch_brick(const float* padded, int px, int py, int pz, int nbx, int nby, int nbz, float out,
                         float* brick, hipStream_t st);
@@ -184,7 +182,34 @@ lg_status check_ligands(const lg_ligands* L, bool need_tors) {
     if (L->tors_offset_host[0] != 0 || L->tors_offset_host[L->n] != L->total_torsions)
       return fail(LG_ERR_INVALID_ARG, "tors_offset does not span [0, total_torsions)");
   }
+  if (L->tors_atoms_host) {
+    if (!L->atom_offset_host || !L->tors_offset_host)
+      return fail(LG_ERR_INVALID_ARG, "tors_atoms_host needs atom_offset_host and tors_offset_host");
+    for (int i = 0; i < L->n; ++i) {
+      const int N = L->atom_offset_host[i + 1] - L->atom_offset_host[i];
+      for (int k = L->tors_offset_host[i]; k < L->tors_offset_host[i + 1]; ++k) {
+        const int a = L->tors_atoms_host[2 * k], b = L->tors_atoms_host[2 * k + 1];
+        if (a < 0 || a >= N || b < 0 || b >= N || a == b)
+          return fail(LG_ERR_INVALID_ARG, "ligand %d: bond %d has atom ids (%d, %d), need two distinct ids in 0..%d",
+                      i, k, a, b, N - 1);
+      }
+    }
+  }
   return LG_OK;
+}
+
+// Largest atom and bond count of a batch whose three host copies were checked by
+// check_ligands; -1 when a copy is missing (the device check then supplies them).
+void host_maxima(const lg_ligands* L, int* max_atoms, int* max_tors) {
+  *max_atoms = *max_tors = -1;
+  if (!L || L->n < 1 || !L->atom_offset_host || !L->tors_offset_host || !L->tors_atoms_host) return;
+  int ma = 0, mt = 0;
+  for (int i = 0; i < L->n; ++i) {
+    ma = std::max(ma, L->atom_offset_host[i + 1] - L->atom_offset_host[i]);
+    mt = std::max(mt, L->tors_offset_host[i + 1] - L->tors_offset_host[i]);
+  }
+  *max_atoms = ma;
+  *max_tors = mt;
 }
 
 // Device-side validation of offsets and bond ids (one small read-back).
@@ -379,8 +404,8 @@ lg_status lg_set_tuning(lg_pocket p, const lg_tuning* t) {
       return fail(LG_ERR_INVALID_ARG, "waves_per_block must be 1, 2 or 4");
   if (t->plain_waves_per_block != 1 && t->plain_waves_per_block != 2 && t->plain_waves_per_block != 4)
     return fail(LG_ERR_INVALID_ARG, "plain_waves_per_block must be 1, 2 or 4");
-  if (t->restart_chunk < 1 || t->grid_scale < 1 || t->grid_scale > 64)
-    return fail(LG_ERR_INVALID_ARG, "restart_chunk >= 1 and grid_scale in 1..64");
+  if (t->restart_chunk < 1 || t->restart_chunk > LG_MAX_RESTARTS || t->grid_scale < 1 || t->grid_scale > 64)
+    return fail(LG_ERR_INVALID_ARG, "restart_chunk in 1..%d and grid_scale in 1..64", LG_MAX_RESTARTS);
   if (t->use_graph != 0 && t->use_graph != 1) return fail(LG_ERR_INVALID_ARG, "use_graph must be 0 or 1");
   if (t->lazy_clash != 0 && t->lazy_clash != 1) return fail(LG_ERR_INVALID_ARG, "lazy_clash must be 0 or 1");
   p->tuning = *t;
@@ -440,11 +465,17 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
   if (L->n == 0) return LG_OK;
   if ((long long)P->restarts * P->sweeps * (6LL * L->n + L->total_torsions) > (1LL << 40))
     return fail(LG_ERR_LIMIT, "R * sweeps * (6 n + total_torsions) move records too large");
+  // the persistent launches take work items (ligand, restart chunk) from a 32-bit
+  // cursor that every wavefront advances once past the end
+  const lg_tuning& tu = p->tuning;
+  if (P->mode == LG_BUCKETED &&
+      (long long)L->n * ((P->restarts + tu.restart_chunk - 1) / tu.restart_chunk) >= (1LL << 30))
+    return fail(LG_ERR_LIMIT, "ligands x restart chunks (%d x %d) must stay below 2^30 work items", L->n,
+                (P->restarts + tu.restart_chunk - 1) / tu.restart_chunk);
   hipStream_t st = (hipStream_t)stream;
   LG_HIP(hipSetDevice(p->device));
 
   const int n = L->n, R = P->restarts;
-  const lg_tuning& tu = p->tuning;
   const int B = tu.n_atom_clusters * tu.n_rot_clusters;
   const DockWs wl = dock_ws_layout(n, R, P->sweeps, L->total_torsions, B);
   const size_t o_final = wl.final_scores, o_moves = wl.moves, o_cls = wl.cls, o_perm = wl.perm, o_cnt = wl.cnt;
@@ -454,7 +485,8 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
   int32_t* stats = (int32_t*)(ws + wl.stats);
 
   int max_atoms = host_max_atoms, max_tors = host_max_tors;
-  if (host_max_atoms < 0) {
+  if (max_atoms < 0) host_maxima(L, &max_atoms, &max_tors);
+  if (max_atoms < 0) {
     s = check_on_device(p, L, stats, st, &max_atoms, &max_tors);
     if (s != LG_OK) return s;
   }
@@ -644,7 +676,7 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
 
 // Host-side validation of a host-resident library (the device check's rules):
 // offsets from 0, non-decreasing, totals; 1..LG_MAX_ATOMS atoms and
-// 0..LG_MAX_TORSIONS bonds per ligand; bond atoms are local ids in range.
+// 0..LG_MAX_TORSIONS bonds per ligand; bond atoms are two distinct local ids.
 lg_status check_host_ligands(const lg_host_ligands* H) {
   if (!H) return fail(LG_ERR_INVALID_ARG, "ligands is NULL");
   if (H->n < 0 || H->total_atoms < 0 || H->total_torsions < 0) return fail(LG_ERR_INVALID_ARG, "negative sizes");
@@ -662,8 +694,8 @@ lg_status check_host_ligands(const lg_host_ligands* H) {
     if (K < 0 || K > LG_MAX_TORSIONS) return fail(LG_ERR_LIMIT, "ligand %d has %d bonds, allowed 0..%d", i, K, LG_MAX_TORSIONS);
     for (int k = H->tors_offset[i]; k < H->tors_offset[i + 1]; ++k)
       if (H->tors_atoms[2 * k] < 0 || H->tors_atoms[2 * k] >= N || H->tors_atoms[2 * k + 1] < 0 ||
-          H->tors_atoms[2 * k + 1] >= N)
-        return fail(LG_ERR_INVALID_ARG, "ligand %d: bond atom ids out of range", i);
+          H->tors_atoms[2 * k + 1] >= N || H->tors_atoms[2 * k] == H->tors_atoms[2 * k + 1])
+        return fail(LG_ERR_INVALID_ARG, "ligand %d: bond %d needs two distinct atom ids in 0..%d", i, k, N - 1);
   }
   return LG_OK;
 }
@@ -846,6 +878,7 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     L.ref_point = (const float*)(d + o_ref);
     L.atom_offset_host = ao;
     L.tors_offset_host = to;
+    L.tors_atoms_host = nullptr;   // checked with the library; maxima passed below
     lg_dock_out DO;
     std::memset(&DO, 0, sizeof DO);
     DO.score = (float*)(d + o_sc);
@@ -1170,40 +1203,6 @@ lg_status lg_autotune(lg_pocket p, const lg_ligands* L, const lg_dock_params* P,
   return LG_OK;
 }
 
-// Workspace of the global ranking: keys, values and members before and after
-// a stable descending radix sort (equal keys keep the lower group first).
-struct RankWs {
-  size_t k0, k1, v0, v1, mem, tmp, tmp_bytes;
-};
-
-static lg_status rank_layout(Layout& lay, int ng, hipStream_t st, RankWs* r) {
-  r->tmp_bytes = 0;
-  LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, r->tmp_bytes, (const float*)nullptr, (float*)nullptr,
-                                                        (const int32_t*)nullptr, (int32_t*)nullptr, ng, 0, 32, st));
-  r->k0 = lay.take((size_t)ng * sizeof(float));
-  r->k1 = lay.take((size_t)ng * sizeof(float));
-  r->v0 = lay.take((size_t)ng * sizeof(int32_t));
-  r->v1 = lay.take((size_t)ng * sizeof(int32_t));
-  r->mem = lay.take((size_t)ng * sizeof(int32_t));
-  r->tmp = lay.take(r->tmp_bytes + 16);
-  return LG_OK;
-}
-
-static lg_status rank_enqueue(lg_pocket p, const RankWs& r, const float* score, int ng, int group, int top_m,
-                              int32_t* top_idx, float* top_score, int32_t* top_member, hipStream_t st) {
-  char* ws = (char*)p->ws;
-  float* k0 = (float*)(ws + r.k0);
-  float* k1 = (float*)(ws + r.k1);
-  int32_t* v0 = (int32_t*)(ws + r.v0);
-  int32_t* v1 = (int32_t*)(ws + r.v1);
-  int32_t* mem = (int32_t*)(ws + r.mem);
-  size_t tmp_bytes = r.tmp_bytes;
-  LG_HIP(lg::launch_rank_prep(score, ng, group, k0, v0, top_member ? mem : nullptr, st));
-  LG_HIP(hipcub::DeviceRadixSort::SortPairsDescending(ws + r.tmp, tmp_bytes, k0, k1, v0, v1, ng, 0, 32, st));
-  LG_HIP(lg::launch_rank_gather(k1, v1, mem, top_m, top_idx, top_score, top_member, st));
-  return LG_OK;
-}
-
 lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, const float* moves, float* score, float* grad,
                    int32_t top_m, int32_t* top_idx, float* top_score, void* stream) {
   if (!p) return fail(LG_ERR_INVALID_ARG, "pocket is NULL");
@@ -1220,21 +1219,21 @@ lg_status lg_score(lg_pocket p, const lg_ligands* L, int32_t interp, const float
   const int n = L->n;
   Layout lay;
   const size_t o_stats = lay.take(16 * sizeof(int32_t));
-  RankWs rw;
-  if (top_m > 0) {
-    s = rank_layout(lay, n, st, &rw);
-    if (s != LG_OK) return s;
-  }
+  const size_t o_rank = top_m > 0 ? lay.take(lg::rank_scratch_bytes(n, top_m)) : 0;
   s = ensure_ws(p, lay.off);
   if (s != LG_OK) return s;
   int max_atoms = 0, max_tors = 0;
-  s = check_on_device(p, L, (int32_t*)((char*)p->ws + o_stats), st, &max_atoms, &max_tors);
-  if (s != LG_OK) return s;
+  host_maxima(L, &max_atoms, &max_tors);
+  if (max_atoms < 0) {
+    s = check_on_device(p, L, (int32_t*)((char*)p->ws + o_stats), st, &max_atoms, &max_tors);
+    if (s != LG_OK) return s;
+  }
   if (moves)
     LG_HIP(lg::launch_score_moves((max_atoms + 63) / 64, p->grid, lig_dev(L), moves, n, score, grad, st));
   else
     LG_HIP(lg::launch_score(p->grid, lig_dev(L), n, interp, score, grad, st));
-  if (top_m > 0) return rank_enqueue(p, rw, score, n, 1, top_m, top_idx, top_score, nullptr, st);
+  if (top_m > 0)
+    LG_HIP(lg::launch_rank(score, n, 1, top_m, (char*)p->ws + o_rank, top_idx, top_score, nullptr, st));
   return LG_OK;
 }
 
@@ -1249,13 +1248,10 @@ lg_status lg_rank(lg_pocket p, const float* score, int32_t n_groups, int32_t gro
   if (top_m == 0) return LG_OK;
   hipStream_t st = (hipStream_t)stream;
   LG_HIP(hipSetDevice(p->device));
-  Layout lay;
-  RankWs rw;
-  lg_status s = rank_layout(lay, n_groups, st, &rw);
+  lg_status s = ensure_ws(p, lg::rank_scratch_bytes(n_groups, top_m));
   if (s != LG_OK) return s;
-  s = ensure_ws(p, lay.off);
-  if (s != LG_OK) return s;
-  return rank_enqueue(p, rw, score, n_groups, group_size, top_m, top_idx, top_score, top_member, st);
+  LG_HIP(lg::launch_rank(score, n_groups, group_size, top_m, p->ws, top_idx, top_score, top_member, st));
+  return LG_OK;
 }
 
 lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp, float* x_out, float* y_out,
@@ -1293,8 +1289,11 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
   if (s != LG_OK) return s;
   char* ws = (char*)p->ws;
   int max_atoms = 0, max_tors = 0;
-  s = check_on_device(p, L, (int32_t*)(ws + o_stats), st, &max_atoms, &max_tors);
-  if (s != LG_OK) return s;
+  host_maxima(L, &max_atoms, &max_tors);
+  if (max_atoms < 0) {
+    s = check_on_device(p, L, (int32_t*)(ws + o_stats), st, &max_atoms, &max_tors);
+    if (s != LG_OK) return s;
+  }
   lg::RefineDev R;
   R.lig_ids = nullptr;
   R.steps = rp->steps;

@@ -51,7 +51,7 @@ class lg_ligands(ctypes.Structure):
                 ("atom_offset", c_void_p), ("tors_offset", c_void_p), ("x", c_void_p), ("y", c_void_p),
                 ("z", c_void_p), ("frag_mask", c_void_p), ("tors_atoms", c_void_p),
                 ("inv_bond_len", c_void_p), ("ref_point", c_void_p), ("atom_offset_host", c_void_p),
-                ("tors_offset_host", c_void_p)]
+                ("tors_offset_host", c_void_p), ("tors_atoms_host", c_void_p)]
 
 
 class lg_dock_params(ctypes.Structure):
@@ -203,6 +203,8 @@ class DeviceLigands:
     ref_point: object
     atom_offset_host: np.ndarray
     tors_offset_host: np.ndarray
+    tors_atoms_host: np.ndarray | None = None
+    host_checks: bool = True   # pass the host copies (checked on the host, no read-back)
 
     @property
     def total_atoms(self) -> int:
@@ -213,11 +215,14 @@ class DeviceLigands:
         return int(self.tors_offset_host[-1])
 
     def struct(self) -> lg_ligands:
+        host = self.host_checks
+        tah = self.tors_atoms_host if host else None
         return lg_ligands(self.n, self.total_atoms, self.total_torsions, _ptr(self.atom_offset),
                           _ptr(self.tors_offset), _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.frag_mask),
                           _ptr(self.tors_atoms), _ptr(self.inv_bond_len), _ptr(self.ref_point),
-                          self.atom_offset_host.ctypes.data_as(c_void_p),
-                          self.tors_offset_host.ctypes.data_as(c_void_p))
+                          self.atom_offset_host.ctypes.data_as(c_void_p) if host else None,
+                          self.tors_offset_host.ctypes.data_as(c_void_p) if host else None,
+                          tah.ctypes.data_as(c_void_p) if tah is not None else None)
 
 
 def device_ligands(atom_offset, tors_offset, x, y, z, frag_mask, tors_atoms, inv_bond_len, ref_point,
@@ -233,9 +238,10 @@ def device_ligands(atom_offset, tors_offset, x, y, z, frag_mask, tors_atoms, inv
 
     ao = np.ascontiguousarray(atom_offset, np.int32)
     to = np.ascontiguousarray(tors_offset, np.int32)
+    ta = np.ascontiguousarray(tors_atoms, np.int32).reshape(-1)
     return DeviceLigands(len(ao) - 1, dev(ao, np.int32), dev(to, np.int32), dev(x, np.float32), dev(y, np.float32),
-                         dev(z, np.float32), dev(frag_mask, np.uint32), dev(tors_atoms, np.int32),
-                         dev(inv_bond_len, np.float32), dev(ref_point, np.float32), ao, to)
+                         dev(z, np.float32), dev(frag_mask, np.uint32), dev(ta, np.int32),
+                         dev(inv_bond_len, np.float32), dev(ref_point, np.float32), ao, to, ta)
 
 
 # ----------------------------------------------------------------- pocket handle
@@ -481,4 +487,4 @@ def docked_poses(ligs: DeviceLigands, out: dict) -> DeviceLigands:
     topology with the output coordinates and pivots (k poses per ligand)."""
     return DeviceLigands(ligs.n, ligs.atom_offset, ligs.tors_offset, out["x"], out["y"], out["z"], ligs.frag_mask,
                          ligs.tors_atoms, ligs.inv_bond_len, out["pivot"].reshape(-1), ligs.atom_offset_host,
-                         ligs.tors_offset_host)
+                         ligs.tors_offset_host, ligs.tors_atoms_host, ligs.host_checks)

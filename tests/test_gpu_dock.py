@@ -202,14 +202,18 @@ def test_device_validation_errors(lgmod, tiny):
     pocket = device_pocket(pk)
     r = torch.from_numpy(tiny["r32"]).cuda()
     a = torch.from_numpy(tiny["a32"]).cuda()
-    bad = L.tors_atoms.copy()
-    bad[1] = 999                                   # moving-side atom out of range
-    dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, bad, L.inv_bond_len,
-                           L.ref_point)
-    with pytest.raises(lg.LgError) as e:
-        lg.lg_dock_batch(pocket, dl, r, a, sweeps=1, top_k=1, trans_samples=64, trans_step=0.0625,
-                         clash_dist2=oracle.CLASH2)
-    assert e.value.status == lg.LG_ERR_INVALID_ARG
+    for fault in ("out of range", "same atom twice"):
+        bad = L.tors_atoms.copy()
+        bad[1] = 999 if fault == "out of range" else bad[0]
+        dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, bad, L.inv_bond_len,
+                               L.ref_point)
+        # checked on the host (host copies given), then by the device check kernel
+        for host in (True, False):
+            dl.host_checks = host
+            with pytest.raises(lg.LgError) as e:
+                lg.lg_dock_batch(pocket, dl, r, a, sweeps=1, top_k=1, trans_samples=64, trans_step=0.0625,
+                                 clash_dist2=oracle.CLASH2)
+            assert e.value.status == lg.LG_ERR_INVALID_ARG, (fault, host)
     with pytest.raises(lg.LgError) as e:
         lg.lg_dock_batch(pocket, device_ligands_ok(lg, L), r, a, sweeps=1, top_k=33, trans_samples=64,
                          trans_step=0.0625, clash_dist2=oracle.CLASH2)
