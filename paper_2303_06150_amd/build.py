@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblg.so")
-SOURCES = ["dock.hip", "aux_kernels.hip", "refine.hip", "api.hip"]
+SOURCES = ["dock.hip", "aux_kernels.hip", "refine.hip", "rank.hip", "api.hip"]
 
 # FP32 contract: no contraction of a*b+c (the kernels spell out every fma),
 # no fast-math.  Packed-FP32 instructions are switched off.

@@ -89,49 +89,6 @@ hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, fl
   return hipGetLastError();
 }
 
-// Sort keys of the global ranking: per group its best value (first member on
-// equal values) as a canonical key (+0 for -0), the group index as the value.
-__global__ void rank_prep_kernel(const float* score, int n_groups, int group, float* keys, int32_t* vals,
-                                 int32_t* member) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_groups) return;
-  const float* s = score + (size_t)i * group;
-  float best = s[0];
-  int bm = 0;
-  for (int q = 1; q < group; ++q)
-    if (s[q] > best) { best = s[q]; bm = q; }
-  keys[i] = best + 0.0f;
-  vals[i] = i;
-  if (member) member[i] = bm;
-}
-
-hipError_t launch_rank_prep(const float* score, int n_groups, int group, float* keys, int32_t* vals,
-                            int32_t* member, hipStream_t st) {
-  if (n_groups == 0) return hipSuccess;
-  hipLaunchKernelGGL(rank_prep_kernel, dim3((n_groups + 255) / 256), dim3(256), 0, st, score, n_groups, group, keys,
-                     vals, member);
-  return hipGetLastError();
-}
-
-// First m entries of the sorted ranking, with the member that gave each group its key.
-__global__ void rank_gather_kernel(const float* keys, const int32_t* vals, const int32_t* member, int m,
-                                   int32_t* top_idx, float* top_score, int32_t* top_member) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const int32_t g = vals[i];
-  top_idx[i] = g;
-  top_score[i] = keys[i];
-  if (top_member) top_member[i] = member[g];
-}
-
-hipError_t launch_rank_gather(const float* keys, const int32_t* vals, const int32_t* member, int m, int32_t* top_idx,
-                              float* top_score, int32_t* top_member, hipStream_t st) {
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(rank_gather_kernel, dim3((m + 255) / 256), dim3(256), 0, st, keys, vals, member, m, top_idx,
-                     top_score, top_member);
-  return hipGetLastError();
-}
-
 // Copy the grid into the padded layout with an out_value border.
 __global__ void pad_kernel(const float* src, int nx, int ny, int nz, float out, float* dst) {
   const long long px = nx + 2, py = ny + 2, pz = nz + 2;

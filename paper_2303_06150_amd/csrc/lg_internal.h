@@ -118,6 +118,14 @@ struct ClusterBounds {
   int rot[32];
 };
 
+// Radix-select state of the global ranking: the selected key prefix and its
+// mask, how many keys of that prefix are still to take, whether the threshold is
+// fixed, and the compaction counter.
+struct RankState {
+  uint64_t prefix, mask;
+  uint32_t need, done, count, pad;
+};
+
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
