@@ -136,41 +136,34 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def replicate(L, count):
-    """count copies of the single ligand of L, as one batch (host arrays)."""
-    N, K = int(L.n_atoms[0]), int(L.n_tors[0])
-    ao = np.arange(count + 1, dtype=np.int32) * N
-    to = np.arange(count + 1, dtype=np.int32) * K
-    tile = lambda a, r=1: np.tile(np.asarray(a), count)
-    return (ao, to, tile(L.x), tile(L.y), tile(L.z), tile(L.frag_mask), tile(L.tors_atoms),
-            tile(L.inv_bond_len), tile(L.ref_point))
-
-
-def experiment_bucket_size(lg, torch, pocket, rt, at, kw, log):
+def experiment_bucket_size(lg, torch, pocket, rt, at, kw, log, sizes=(17, 53, 99),
+                           multiples=(1, 2, 3, 4, 5, 6, 9, 12, 24), min_ligands=2000):
     """The bucket-size experiment of Sec. 5 (Fig. 2) on synthetic replicas: one
     ligand of 17, 53 or 99 atoms replicated, docked in batches of l ligands;
-    throughput against l.  l_fill = resident wavefronts x restart chunk / R is the
-    batch that fills the chip once (one wavefront per work item of chunk restarts),
-    the MI355X form of Eq. 1 for this mapping."""
+    throughput against l at multiples of a third of l_fill.  l_fill = resident
+    wavefronts x restart chunk / R is the batch that fills the chip once (one
+    wavefront per work item of chunk restarts), the MI355X form of Eq. 1 for this
+    mapping."""
     import gen
     t = pocket.get_tuning()
     rows = []
-    for N in (17, 53, 99):
-        K = int(round(0.18 * N))
-        L1 = gen.ligands_from_sizes(np.array([9_000_000 + N]), 0, np.array([N]), np.array([K]))
-        probe = lg.device_ligands(*replicate(L1, 64))
-        lg.lg_dock_batch(pocket, probe, rt, at, mode=lg.LG_BUCKETED, **kw)
+    for N in sizes:
+        L1 = gen.replica_ligand(N)
+        K = int(L1.n_tors[0])
+        dev = lambda L: lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                                          L.inv_bond_len, L.ref_point)
+        lg.lg_dock_batch(pocket, dev(gen.replicas(L1, 64)), rt, at, mode=lg.LG_BUCKETED, **kw)
         torch.cuda.synchronize()
         st = pocket.bucket_stats()
         waves = max(b["blocks"] * b["waves_per_block"] for b in st)
         R = int(rt.shape[0])
         l_fill = max(1, waves * t.restart_chunk // R)
-        for m in (1, 2, 3, 4, 5, 6, 9, 12, 24):
+        for m in multiples:
             l = max(1, l_fill * m // 3)
-            dl = lg.device_ligands(*replicate(L1, l))
+            dl = dev(gen.replicas(L1, l))
             out = lg.lg_dock_batch(pocket, dl, rt, at, mode=lg.LG_BUCKETED, **kw)
             torch.cuda.synchronize()
-            reps = max(1, -(-max(2000, 4 * l) // l))
+            reps = max(1, -(-max(min_ligands, 4 * l) // l))
             t0 = time.perf_counter()
             for _ in range(reps):
                 out = lg.lg_dock_batch(pocket, dl, rt, at, mode=lg.LG_BUCKETED, out=out, **kw)

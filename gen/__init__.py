@@ -226,6 +226,25 @@ def ligands_from_sizes(ids, seed: int, n_req, k_req) -> Ligands:
                    inv_f.astype(np.float32), inv64, ref_f.astype(np.float32).reshape(-1), ref64.reshape(-1))
 
 
+def replica_ligand(N: int, seed: int = 0) -> Ligands:
+    """The one ligand of N atoms (round(0.18 N) rotatable bonds) that the
+    batch-size experiment replicates (the paper replicates three ligands of 17,
+    53 and 99 atoms); its generator item id is 9_000_000 + N."""
+    return ligands_from_sizes(np.array([9_000_000 + N]), seed, np.array([N]), np.array([int(round(0.18 * N))]))
+
+
+def replicas(L1: Ligands, count: int) -> Ligands:
+    """count copies of the single ligand of L1, as one batch."""
+    N, K = int(L1.n_atoms[0]), int(L1.n_tors[0])
+    tile = lambda a: np.tile(np.asarray(a), count)
+    ao = np.arange(count + 1, dtype=np.int32) * N
+    to = np.arange(count + 1, dtype=np.int32) * K
+    return Ligands(np.full(count, L1.ids[0]), np.full(count, N, np.int32), np.full(count, K, np.int32), ao, to,
+                   tile(L1.x), tile(L1.y), tile(L1.z), np.tile(L1.xyz64, (count, 1)), tile(L1.parent),
+                   tile(L1.frag_mask), tile(L1.tors_atoms), tile(L1.inv_bond_len), tile(L1.inv_bond_len64),
+                   tile(L1.ref_point), tile(L1.ref_point64))
+
+
 # ------------------------------------------------------------------- tables
 def restarts(R: int, seed: int = 0, radius: float = 2.0):
     """[R,12] restart table: row-major rotation then offset; row 0 identity."""

@@ -1,12 +1,14 @@
 """lg_dock_stream: a host-resident library streamed through the device in
 chunks (pinned staging, copy-in / dock / copy-out overlapped, two buffer
-slots) gives exactly what lg_dock_batch gives on the whole library."""
+slots) gives exactly what lg_dock_batch gives on the whole library, and on
+sampled ligands (first chunk, a middle chunk, the ragged last chunk) exactly
+the oracle's top-k."""
 import numpy as np
 import pytest
 
 import gen
 import oracle
-from gpu_common import device_pocket, say
+from gpu_common import device_pocket, dock_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +39,20 @@ def test_stream_equals_batch(n, chunk):
     got = lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, **kw)
     for key in ("score", "restart_id", "x", "y", "z", "pivot"):
         np.testing.assert_array_equal(got[key], ref[key].cpu().numpy(), err_msg=key)
+    if chunk == 700:
+        k = w.top_k
+        for i in (3, 1750, n - 1):            # chunks 0, 2 and the ragged last one
+            o = dock_oracle(pk, L, i, r32, a32, T=T, S=w.sweeps)
+            idx = oracle.topk(o["final"], k)
+            np.testing.assert_array_equal(got["restart_id"][i], idx, err_msg=f"ligand {i} ids")
+            np.testing.assert_array_equal(got["score"][i].astype(np.float64), o["final"][idx])
+            np.testing.assert_array_equal(got["pivot"][i].astype(np.float64), o["pivots"][idx])
+            a0, N = int(L.atom_offset[i]), int(L.n_atoms[i])
+            for q in range(k):
+                b = k * a0 + q * N
+                pose = np.stack([got[c][b:b + N] for c in ("x", "y", "z")], 1).astype(np.float64)
+                np.testing.assert_array_equal(pose, o["poses"][idx[q]], err_msg=f"ligand {i} rank {q}")
+            say(f"  streamed ligand {i} (N={N}) equals the oracle's top-{k}")
     pocket.free()
 
 
