@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblg.so")
-SOURCES = ["dock.hip", "aux_kernels.hip", "refine.hip", "rank.hip", "api.hip"]
+SOURCES = ["dock.hip", "aux_kernels.hip", "refine.hip", "rank.hip", "api.hip", "host_checks.cpp"]
 
 # FP32 contract: no contraction of a*b+c (the kernels spell out every fma),
 # no fast-math.  Packed-FP32 instructions are switched off.
@@ -34,7 +34,7 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
 
     def compile_one(src):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:

@@ -8,10 +8,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include "host_checks.h"
 #include "lg.h"
 #include "lg_internal.h"
 
@@ -47,17 +49,12 @@ hipError_t launch_check(const int32_t* atom_offset, const int32_t* tors_offset, 
 
 namespace {
 
-thread_local std::string g_err;
-
-lg_status fail(lg_status s, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return s;
-}
+using lghost::fail;
+using lghost::env_ll;
+using lghost::workspace_limit;
+using lghost::check_ligands;
+using lghost::host_maxima;
+using lghost::check_host_ligands;
 
 #define LG_HIP(call)                                                                          \
   do {                                                                                        \
@@ -132,8 +129,12 @@ namespace {
 
 constexpr size_t kBranches = 3;   // with the launching stream: up to 4 buckets in flight
 
+
 lg_status ensure_ws(lg_pocket p, size_t bytes) {
   if (bytes <= p->ws_bytes) return LG_OK;
+  const size_t limit = workspace_limit();
+  if (bytes > limit)
+    return fail(LG_ERR_OUT_OF_MEMORY, "workspace of %zu bytes exceeds LG_WORKSPACE_LIMIT = %zu", bytes, limit);
   if (p->gexec) {
     (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -145,7 +146,7 @@ lg_status ensure_ws(lg_pocket p, size_t bytes) {
     p->ws = nullptr;
     p->ws_bytes = 0;
   }
-  size_t want = bytes + bytes / 8;
+  size_t want = std::min(bytes + bytes / 8, limit);
   if (hipMalloc(&p->ws, want) != hipSuccess) {
     (void)hipGetLastError();
     p->ws = nullptr;
@@ -155,62 +156,6 @@ lg_status ensure_ws(lg_pocket p, size_t bytes) {
   return LG_OK;
 }
 
-lg_status check_ligands(const lg_ligands* L, bool need_tors) {
-  if (!L) return fail(LG_ERR_INVALID_ARG, "ligands is NULL");
-  if (L->n < 0) return fail(LG_ERR_INVALID_ARG, "n = %d < 0", L->n);
-  if (L->n == 0) return LG_OK;
-  if (!L->atom_offset || !L->tors_offset || !L->x || !L->y || !L->z || !L->ref_point)
-    return fail(LG_ERR_INVALID_ARG, "a required ligand array is NULL");
-  if (need_tors && (!L->frag_mask || (L->total_torsions > 0 && (!L->tors_atoms || !L->inv_bond_len))))
-    return fail(LG_ERR_INVALID_ARG, "a required ligand array is NULL");
-  if (L->total_atoms < L->n || L->total_torsions < 0) return fail(LG_ERR_INVALID_ARG, "bad total sizes");
-  if (L->total_atoms > (1 << 30) - 256)
-    return fail(LG_ERR_LIMIT, "total_atoms %d above 2^30 - 256 (32-bit byte offsets)", L->total_atoms);
-  if (L->atom_offset_host) {
-    for (int i = 0; i < L->n; ++i) {
-      int N = L->atom_offset_host[i + 1] - L->atom_offset_host[i];
-      if (N < 1 || N > LG_MAX_ATOMS) return fail(LG_ERR_LIMIT, "ligand %d has %d atoms (1..%d)", i, N, LG_MAX_ATOMS);
-    }
-    if (L->atom_offset_host[0] != 0 || L->atom_offset_host[L->n] != L->total_atoms)
-      return fail(LG_ERR_INVALID_ARG, "atom_offset does not span [0, total_atoms)");
-  }
-  if (L->tors_offset_host) {
-    for (int i = 0; i < L->n; ++i) {
-      int K = L->tors_offset_host[i + 1] - L->tors_offset_host[i];
-      if (K < 0 || K > LG_MAX_TORSIONS) return fail(LG_ERR_LIMIT, "ligand %d has %d bonds (0..%d)", i, K, LG_MAX_TORSIONS);
-    }
-    if (L->tors_offset_host[0] != 0 || L->tors_offset_host[L->n] != L->total_torsions)
-      return fail(LG_ERR_INVALID_ARG, "tors_offset does not span [0, total_torsions)");
-  }
-  if (L->tors_atoms_host) {
-    if (!L->atom_offset_host || !L->tors_offset_host)
-      return fail(LG_ERR_INVALID_ARG, "tors_atoms_host needs atom_offset_host and tors_offset_host");
-    for (int i = 0; i < L->n; ++i) {
-      const int N = L->atom_offset_host[i + 1] - L->atom_offset_host[i];
-      for (int k = L->tors_offset_host[i]; k < L->tors_offset_host[i + 1]; ++k) {
-        const int a = L->tors_atoms_host[2 * k], b = L->tors_atoms_host[2 * k + 1];
-        if (a < 0 || a >= N || b < 0 || b >= N || a == b)
-          return fail(LG_ERR_INVALID_ARG, "ligand %d: bond %d has atom ids (%d, %d), need two distinct ids in 0..%d",
-                      i, k, a, b, N - 1);
-      }
-    }
-  }
-  return LG_OK;
-}
-
-// Largest atom and bond count of a batch whose three host copies were checked by
-// check_ligands; -1 when a copy is missing (the device check then supplies them).
-void host_maxima(const lg_ligands* L, int* max_atoms, int* max_tors) {
-  *max_atoms = *max_tors = -1;
-  if (!L || L->n < 1 || !L->atom_offset_host || !L->tors_offset_host || !L->tors_atoms_host) return;
-  int ma = 0, mt = 0;
-  for (int i = 0; i < L->n; ++i) {
-    ma = std::max(ma, L->atom_offset_host[i + 1] - L->atom_offset_host[i]);
-    mt = std::max(mt, L->tors_offset_host[i + 1] - L->tors_offset_host[i]);
-  }
-  *max_atoms = ma;
-  *max_tors = mt;
-}
 
 // Device-side validation of offsets and bond ids (one small read-back).
 lg_status check_on_device(lg_pocket p, const lg_ligands* L, int32_t* dstats, hipStream_t st, int* max_atoms,
@@ -248,37 +193,6 @@ lg::LigDev lig_dev(const lg_ligands* L) {
 
 extern "C" {
 
-const char* lg_last_error(void) { return g_err.c_str(); }
-
-int32_t lg_version(void) { return 1; }
-
-int64_t lg_bucket_size(int64_t blocks_per_unit, int64_t units, int64_t threads_per_block, int64_t wave_size) {
-  if (blocks_per_unit < 0 || units < 0 || threads_per_block <= 0 || wave_size <= 0) return -1;
-  return blocks_per_unit * units * threads_per_block / wave_size;
-}
-
-int32_t lg_atom_clusters(int32_t n_clusters, int32_t wave_size, int32_t max_atoms, int32_t* bounds) {
-  if (n_clusters < 1 || wave_size < 1 || max_atoms < 1 || !bounds) return 0;
-  int c = 0;
-  for (; c < n_clusters - 1 && (c + 1) * wave_size < max_atoms; ++c) bounds[c] = (c + 1) * wave_size;
-  bounds[c++] = max_atoms;
-  return c;
-}
-
-int32_t lg_rotamer_clusters(int32_t n_clusters, int32_t max_rot, int32_t* bounds) {
-  if (n_clusters < 1 || max_rot < 0 || !bounds) return 0;
-  int c = 0, prev = -1;
-  for (int i = 0; i < n_clusters - 1; ++i) {
-    double f = (double)(i + 1) / n_clusters;
-    int b = (int)std::lround(max_rot * f * f);
-    b = std::max(b, prev + 1);
-    if (b >= max_rot) break;
-    bounds[c++] = b;
-    prev = b;
-  }
-  bounds[c++] = max_rot;
-  return c;
-}
 
 lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t grid_is_device, void* stream,
                          lg_pocket* out) {
@@ -391,23 +305,8 @@ lg_status lg_free_pocket(lg_pocket p) {
 
 lg_status lg_set_tuning(lg_pocket p, const lg_tuning* t) {
   if (!p || !t) return fail(LG_ERR_INVALID_ARG, "pocket and tuning must not be NULL");
-  if (t->n_atom_clusters < 1 || t->n_atom_clusters > 16 || t->n_rot_clusters < 1 || t->n_rot_clusters > 32)
-    return fail(LG_ERR_INVALID_ARG, "cluster counts out of range");
-  for (int c = 0; c < t->n_atom_clusters; ++c)
-    if (t->atom_bounds[c] < 1 || t->atom_bounds[c] > LG_MAX_ATOMS || (c && t->atom_bounds[c] <= t->atom_bounds[c - 1]))
-      return fail(LG_ERR_INVALID_ARG, "atom bounds must increase within 1..%d", LG_MAX_ATOMS);
-  for (int c = 0; c < t->n_rot_clusters; ++c)
-    if (t->rot_bounds[c] < 0 || t->rot_bounds[c] > LG_MAX_TORSIONS || (c && t->rot_bounds[c] <= t->rot_bounds[c - 1]))
-      return fail(LG_ERR_INVALID_ARG, "rotamer bounds must increase within 0..%d", LG_MAX_TORSIONS);
-  for (int i = 0; i < 4; ++i)
-    if (t->waves_per_block[i] != 1 && t->waves_per_block[i] != 2 && t->waves_per_block[i] != 4)
-      return fail(LG_ERR_INVALID_ARG, "waves_per_block must be 1, 2 or 4");
-  if (t->plain_waves_per_block != 1 && t->plain_waves_per_block != 2 && t->plain_waves_per_block != 4)
-    return fail(LG_ERR_INVALID_ARG, "plain_waves_per_block must be 1, 2 or 4");
-  if (t->restart_chunk < 1 || t->restart_chunk > LG_MAX_RESTARTS || t->grid_scale < 1 || t->grid_scale > 64)
-    return fail(LG_ERR_INVALID_ARG, "restart_chunk in 1..%d and grid_scale in 1..64", LG_MAX_RESTARTS);
-  if (t->use_graph != 0 && t->use_graph != 1) return fail(LG_ERR_INVALID_ARG, "use_graph must be 0 or 1");
-  if (t->lazy_clash != 0 && t->lazy_clash != 1) return fail(LG_ERR_INVALID_ARG, "lazy_clash must be 0 or 1");
+  lg_status s = lghost::check_tuning(t);
+  if (s != LG_OK) return s;
   p->tuning = *t;
   if (p->gexec) {
     (void)hipGraphExecDestroy(p->gexec);
@@ -674,31 +573,6 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
   return LG_OK;
 }
 
-// Host-side validation of a host-resident library (the device check's rules):
-// offsets from 0, non-decreasing, totals; 1..LG_MAX_ATOMS atoms and
-// 0..LG_MAX_TORSIONS bonds per ligand; bond atoms are two distinct local ids.
-lg_status check_host_ligands(const lg_host_ligands* H) {
-  if (!H) return fail(LG_ERR_INVALID_ARG, "ligands is NULL");
-  if (H->n < 0 || H->total_atoms < 0 || H->total_torsions < 0) return fail(LG_ERR_INVALID_ARG, "negative sizes");
-  if (!H->atom_offset || !H->tors_offset) return fail(LG_ERR_INVALID_ARG, "offsets are required");
-  if (H->n > 0 && (!H->x || !H->y || !H->z || !H->frag_mask || !H->ref_point))
-    return fail(LG_ERR_INVALID_ARG, "x, y, z, frag_mask and ref_point are required");
-  if (H->total_torsions > 0 && (!H->tors_atoms || !H->inv_bond_len))
-    return fail(LG_ERR_INVALID_ARG, "tors_atoms and inv_bond_len are required");
-  if (H->atom_offset[0] != 0 || H->tors_offset[0] != 0 || H->atom_offset[H->n] != H->total_atoms ||
-      H->tors_offset[H->n] != H->total_torsions)
-    return fail(LG_ERR_INVALID_ARG, "offsets must start at 0 and end at the totals");
-  for (int i = 0; i < H->n; ++i) {
-    const int N = H->atom_offset[i + 1] - H->atom_offset[i], K = H->tors_offset[i + 1] - H->tors_offset[i];
-    if (N < 1 || N > LG_MAX_ATOMS) return fail(LG_ERR_LIMIT, "ligand %d has %d atoms, allowed 1..%d", i, N, LG_MAX_ATOMS);
-    if (K < 0 || K > LG_MAX_TORSIONS) return fail(LG_ERR_LIMIT, "ligand %d has %d bonds, allowed 0..%d", i, K, LG_MAX_TORSIONS);
-    for (int k = H->tors_offset[i]; k < H->tors_offset[i + 1]; ++k)
-      if (H->tors_atoms[2 * k] < 0 || H->tors_atoms[2 * k] >= N || H->tors_atoms[2 * k + 1] < 0 ||
-          H->tors_atoms[2 * k + 1] >= N || H->tors_atoms[2 * k] == H->tors_atoms[2 * k + 1])
-        return fail(LG_ERR_INVALID_ARG, "ligand %d: bond %d needs two distinct atom ids in 0..%d", i, k, N - 1);
-  }
-  return LG_OK;
-}
 
 extern "C" {
 
@@ -781,6 +655,9 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     if (cin) (void)hipStreamDestroy(cin);
     if (cout) (void)hipStreamDestroy(cout);
   };
+  if (2 * slot_bytes > workspace_limit())
+    return fail(LG_ERR_OUT_OF_MEMORY, "stream buffers of 2 x %zu bytes exceed LG_WORKSPACE_LIMIT = %zu", slot_bytes,
+                workspace_limit());
   bool ok = true;
   for (int i = 0; i < 2 && ok; ++i) {
     ok = hipMalloc((void**)&dev[i], slot_bytes) == hipSuccess &&
@@ -820,7 +697,10 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
   };
 
   const int nc = (int)todo.size();
+  const long long fault_after = env_ll("LG_FAULT_AFTER_CHUNKS", -1);
+  int enq = 0;   // chunks of todo enqueued (docking and copy-back)
   for (int ci = 0; ci < nc && s == LG_OK; ++ci) {
+    if (ci == fault_after) break;
     const Chunk& c = chunks[todo[ci]];
     const int sl = ci % 2;
     char* h = host[sl];
@@ -902,9 +782,10 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
       if (e == hipSuccess) e = copy(h + off, d + off, (size_t)k * na * 4, hipMemcpyDeviceToHost, cout);
     if (e == hipSuccess) e = hipEventRecord(ev_out[sl], cout);
     if (e != hipSuccess) { s = fail(LG_ERR_DEVICE, "stream copy-out failed: %s", hipGetErrorString(e)); break; }
+    enq = ci + 1;
   }
-  // the last two chunks
-  for (int ci = std::max(0, nc - 2); ci < nc && s == LG_OK; ++ci) {
+  // the last two chunks enqueued
+  for (int ci = std::max(0, enq - 2); ci < enq && s == LG_OK; ++ci) {
     if (hipEventSynchronize(ev_out[ci % 2]) != hipSuccess) {
       s = fail(LG_ERR_DEVICE, "stream copy-back failed");
       break;
@@ -912,6 +793,8 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     unpack(ci);
   }
   release();
+  if (s == LG_OK && enq < nc)
+    s = fail(LG_ERR_DEVICE, "stopped after %d of %d chunks (LG_FAULT_AFTER_CHUNKS)", enq, nc);
   return s;
 }
 

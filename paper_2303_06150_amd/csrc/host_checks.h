@@ -1,0 +1,28 @@
+// Host-side checks of the C ABI's arguments, in plain C++ (no device code), so
+// that they also build with the host compiler's address and undefined-behaviour
+// sanitizers: ligand batches (device batches with optional host copies, and
+// host-resident libraries), tunings, and the host-only calls (Eq. 1, cluster
+// boundaries, the last error message).  The check functions report failures
+// through fail(), which records the message lg_last_error() returns.
+#pragma once
+#include <cstddef>
+
+#include "lg.h"
+
+namespace lghost {
+
+lg_status fail(lg_status s, const char* fmt, ...);
+
+// Environment controls read at every call (a non-negative integer, else dflt).
+long long env_ll(const char* name, long long dflt);
+size_t workspace_limit();
+
+// A device batch: sizes, limits and (when host copies are given) offsets and bond ids.
+lg_status check_ligands(const lg_ligands* L, bool need_tors);
+// Largest atom and bond count from the three host copies, or -1 when one is missing.
+void host_maxima(const lg_ligands* L, int* max_atoms, int* max_tors);
+// A host-resident library (lg_dock_stream): the device check's rules, on the host.
+lg_status check_host_ligands(const lg_host_ligands* H);
+lg_status check_tuning(const lg_tuning* t);
+
+}  // namespace lghost
