@@ -247,7 +247,13 @@ typedef struct {
  * validated on the host first (same rules as lg_dock_batch's device check).
  * Results are those of lg_dock_batch on the whole library in LG_BUCKETED mode;
  * params' tables are device memory.  Returns when every result is in `out`.
- * Calls on one handle must not overlap. */
+ * Calls on one handle must not overlap.  On an error after some chunks, those
+ * chunks' outputs and manifest entries are complete and the others untouched,
+ * so a call with the same arrays resumes.  For tests of that path, the
+ * environment variable LG_FAULT_AFTER_CHUNKS=k stops a call with LG_ERR_DEVICE
+ * after k chunks; LG_WORKSPACE_LIMIT (bytes) caps the docking workspace of a
+ * handle and the stream buffers (LG_ERR_OUT_OF_MEMORY above it, before any
+ * work). */
 lg_status lg_dock_stream(lg_pocket pocket, const lg_host_ligands* ligands, const lg_dock_params* params,
                          int32_t chunk, const lg_host_out* out, void* stream);
 

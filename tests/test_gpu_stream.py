@@ -135,3 +135,58 @@ def test_stream_resumes_from_manifest(tmp_path):
     # every chunk finished: nothing to do
     lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, out=out, chunk_done=done, **kw)
     pocket.free()
+
+
+def test_stream_fault_after_chunks_then_resume(monkeypatch):
+    """A run forced to stop after 3 chunks (LG_FAULT_AFTER_CHUNKS, a host-side
+    switch) returns LG_ERR_DEVICE with exactly those chunks written and marked;
+    the next call with the same arrays finishes the rest, and the result equals
+    an uninterrupted run.  LG_WORKSPACE_LIMIT turns an oversized workspace into
+    LG_ERR_OUT_OF_MEMORY before any work."""
+    import torch
+    from paper_2303_06150_amd import lg
+    lg.load_library()
+    w = gen.WORKLOADS["mixed"]
+    n, chunk = 2500, 400
+    L = gen.workload_ligands(w, np.arange(n, dtype=np.int64))
+    pk = gen.workload_pocket(w)
+    r32, _ = gen.restarts(w.restarts, w.seed)
+    a32, _ = gen.angles(w.angle_samples)
+    pocket = device_pocket(pk)
+    rt, at = torch.from_numpy(r32).cuda(), torch.from_numpy(a32).cuda()
+    T, k = w.angle_samples, w.top_k
+    kw = dict(sweeps=w.sweeps, top_k=k, trans_samples=T, trans_step=oracle.trans_step(T), clash_dist2=oracle.CLASH2)
+    ref = lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, **kw)
+    nch = -(-n // chunk)
+    out = {key: np.full_like(v, -7) for key, v in ref.items()}
+    done = np.zeros(nch, np.int32)
+    say("stream: forced stop after 3 chunks, then resume")
+    monkeypatch.setenv("LG_FAULT_AFTER_CHUNKS", "3")
+    with pytest.raises(lg.LgError) as e:
+        lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, out=out, chunk_done=done, **kw)
+    assert e.value.status == lg.LG_ERR_DEVICE and "3 of 7" in lg.lg_last_error()
+    np.testing.assert_array_equal(done, [1, 1, 1, 0, 0, 0, 0])
+    i3, a3 = 3 * chunk, int(L.atom_offset[3 * chunk])
+    for key in ("score", "restart_id", "pivot"):
+        np.testing.assert_array_equal(out[key][:i3], ref[key][:i3], err_msg=key)
+        assert (out[key][i3:] == -7).all(), key
+    for key in ("x", "y", "z"):
+        np.testing.assert_array_equal(out[key][:k * a3], ref[key][:k * a3], err_msg=key)
+        assert (out[key][k * a3:] == -7).all(), key
+    monkeypatch.delenv("LG_FAULT_AFTER_CHUNKS")
+    lg.lg_dock_stream(pocket, *host_args(L), rt, at, chunk=chunk, out=out, chunk_done=done, **kw)
+    assert (done == 1).all()
+    for key in ref:
+        np.testing.assert_array_equal(out[key], ref[key], err_msg=key)
+    pocket.free()
+    fresh = device_pocket(pk)
+    monkeypatch.setenv("LG_WORKSPACE_LIMIT", "4096")
+    dl = lg.device_ligands(*host_args(L))
+    with pytest.raises(lg.LgError) as e:
+        lg.lg_dock_batch(fresh, dl, rt, at, **kw)
+    assert e.value.status == lg.LG_ERR_OUT_OF_MEMORY and "LG_WORKSPACE_LIMIT" in lg.lg_last_error()
+    with pytest.raises(lg.LgError) as e:
+        lg.lg_dock_stream(fresh, *host_args(L), rt, at, chunk=chunk, **kw)
+    assert e.value.status == lg.LG_ERR_OUT_OF_MEMORY
+    monkeypatch.delenv("LG_WORKSPACE_LIMIT")
+    fresh.free()
