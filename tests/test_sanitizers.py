@@ -18,8 +18,10 @@ def build_and_run(tmp_path, name, sources, extra=()):
     exe = str(tmp_path / name)
     cmd = ["g++", *SAN, *extra, *[os.path.join(ROOT, s) for s in sources], "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
-    env.pop("LD_PRELOAD", None)
+    # the environment is passed on unchanged; ASan is told not to insist on being
+    # first in the initial library list
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     return r.stdout
