@@ -309,6 +309,22 @@ lg_status lg_refine(lg_pocket pocket, const lg_ligands* poses, const lg_refine_p
 lg_status lg_rank(lg_pocket pocket, const float* score, int32_t n_groups, int32_t group_size, int32_t top_m,
                   int32_t* top_idx, float* top_score, int32_t* top_member, void* stream);
 
+/* lg_rank for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments and results as lg_rank, no pocket handle, and no allocation of any
+ * kind.  Its scratch is a fixed device array in the library (about 12 MiB,
+ * one copy per device, held until the process ends), looked up on the first
+ * call on each device; the device is the caller's current device, which must
+ * own `stream` and the buffers.  Limits: n_groups <= LG_RANK_STATIC_MAX_GROUPS
+ * and top_m <= LG_RANK_STATIC_MAX_TOP, else LG_ERR_LIMIT before any device
+ * work.  Every call on one device shares that array (each call re-initialises
+ * what it reads, on `stream`): calls that overlap on one device -- concurrent
+ * streams or threads -- race and give wrong results; serialise them. */
+#define LG_RANK_STATIC_MAX_GROUPS (1 << 20)
+#define LG_RANK_STATIC_MAX_TOP 4096
+lg_status lg_rank_static(const float* score, int32_t n_groups, int32_t group_size, int32_t top_m,
+                         int32_t* top_idx, float* top_score, int32_t* top_member, void* stream);
+
 /* Tuning of the bucketed path; the autotuner sets it, the defaults work.
  * Ligands go to bucket (atom cluster, rotamer cluster): atom cluster c holds
  * atoms <= atom_bounds[c] (first match), rotamer cluster c bonds <=

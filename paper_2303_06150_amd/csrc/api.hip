@@ -32,8 +32,9 @@ hipError_t launch_topk(int nslot, const LigDev& Lg, const DockDev& D, int n, int
 hipError_t launch_score(const GridDev& G, const LigDev& P, int n, int interp, float* score, float* grad,
                         hipStream_t st);
 size_t rank_scratch_bytes(int n, int m);
-hipError_t launch_rank(const float* score, int n, int group, int m, void* scratch, int32_t* top_idx,
+hipError_t launch_rank(const float* score, int n, int group, int m, void* work, int32_t* top_idx,
                        float* top_score, int32_t* top_member, hipStream_t st);
+hipError_t rank_static_scratch(void** out, size_t* bytes);
 hipError_t launch_pad(const float* src, int nx, int ny, int nz, float out, float* dst, hipStream_t st);
 hipError_t launch_brick(const float* padded, int px, int py, int pz, int nbx, int nby, int nbz, float out,
                         float* brick, hipStream_t st);
@@ -1134,6 +1135,28 @@ lg_status lg_rank(lg_pocket p, const float* score, int32_t n_groups, int32_t gro
   lg_status s = ensure_ws(p, lg::rank_scratch_bytes(n_groups, top_m));
   if (s != LG_OK) return s;
   LG_HIP(lg::launch_rank(score, n_groups, group_size, top_m, p->ws, top_idx, top_score, top_member, st));
+  return LG_OK;
+}
+
+lg_status lg_rank_static(const float* score, int32_t n_groups, int32_t group_size, int32_t top_m,
+                         int32_t* top_idx, float* top_score, int32_t* top_member, void* stream) {
+  if (n_groups < 0 || group_size < 1) return fail(LG_ERR_INVALID_ARG, "n_groups %d < 0 or group_size %d < 1", n_groups, group_size);
+  if ((long long)n_groups * group_size > INT32_MAX) return fail(LG_ERR_LIMIT, "n_groups * group_size exceeds 2^31 - 1");
+  if (top_m < 0 || top_m > n_groups) return fail(LG_ERR_INVALID_ARG, "top_m %d outside 0..n_groups", top_m);
+  if (n_groups > LG_RANK_STATIC_MAX_GROUPS || top_m > LG_RANK_STATIC_MAX_TOP)
+    return fail(LG_ERR_LIMIT, "n_groups %d or top_m %d above the fixed scratch's %d / %d", n_groups, top_m,
+                LG_RANK_STATIC_MAX_GROUPS, LG_RANK_STATIC_MAX_TOP);
+  if (n_groups > 0 && !score) return fail(LG_ERR_INVALID_ARG, "score is NULL");
+  if (top_m > 0 && (!top_idx || !top_score)) return fail(LG_ERR_INVALID_ARG, "top_idx and top_score are required for top_m > 0");
+  if (top_m == 0) return LG_OK;
+  void* work = nullptr;
+  size_t bytes = 0;
+  LG_HIP(lg::rank_static_scratch(&work, &bytes));
+  if (lg::rank_scratch_bytes(n_groups, top_m) > bytes)
+    return fail(LG_ERR_LIMIT, "ranking needs %zu bytes of scratch, the fixed array holds %zu",
+                lg::rank_scratch_bytes(n_groups, top_m), bytes);
+  LG_HIP(lg::launch_rank(score, n_groups, group_size, top_m, work, top_idx, top_score, top_member,
+                         (hipStream_t)stream));
   return LG_OK;
 }
 

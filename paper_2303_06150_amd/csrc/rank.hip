@@ -14,9 +14,11 @@
 // of the m keys >= that threshold (wave-aggregated counter); (4) a descending
 // bitonic sort of the m keys, in LDS for m <= 4096, else tile sorts in LDS plus
 // global merge steps; (5) ids, values and members of the sorted keys.
+#include "lg.h"
 #include "lg_internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace lg {
 
@@ -177,19 +179,54 @@ long long pow2_at_least(long long m) {
   return p;
 }
 
-}  // namespace
+constexpr size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t rank_scratch_bytes(int n, int m) {
-  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  return up(sizeof(RankState)) + up(256 * sizeof(uint32_t)) + up((size_t)n * 8) + up((size_t)n * 4) +
-         up((size_t)pow2_at_least(m < 1 ? 1 : m) * 8);
+constexpr size_t scratch_bytes(size_t n, size_t pow2_m) {
+  return up256(sizeof(RankState)) + up256(256 * sizeof(uint32_t)) + up256(n * 8) + up256(n * 4) +
+         up256(pow2_m * 8);
 }
 
-hipError_t launch_rank(const float* score, int n, int group, int m, void* scratch, int32_t* top_idx,
+// Fixed device scratch of lg_rank_static, sized for its largest accepted call
+// (LG_RANK_STATIC_MAX_TOP is a power of two).  Every device the library runs on
+// holds one copy until the process ends.  Host code must not pass this name to
+// a kernel: its device address comes from hipGetSymbolAddress.
+static_assert((LG_RANK_STATIC_MAX_TOP & (LG_RANK_STATIC_MAX_TOP - 1)) == 0, "power of two");
+constexpr size_t kStaticScratchBytes = scratch_bytes(LG_RANK_STATIC_MAX_GROUPS, LG_RANK_STATIC_MAX_TOP);
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+size_t rank_scratch_bytes(int n, int m) { return scratch_bytes((size_t)n, (size_t)pow2_at_least(m < 1 ? 1 : m)); }
+
+// Device address of the current device's copy of the fixed scratch, looked up
+// once per device (with that device current) and kept.
+hipError_t rank_static_scratch(void** out, size_t* bytes) {
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  *bytes = kStaticScratchBytes;
+  return hipSuccess;
+}
+
+hipError_t launch_rank(const float* score, int n, int group, int m, void* work, int32_t* top_idx,
                        float* top_score, int32_t* top_member, hipStream_t st) {
   if (n <= 0 || m <= 0) return hipSuccess;
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  char* w = (char*)scratch;
+  char* w = (char*)work;
   RankState* state = (RankState*)w;
   w += up(sizeof(RankState));
   uint32_t* hist = (uint32_t*)w;

@@ -26,7 +26,7 @@ LG_PLAIN, LG_BUCKETED = 0, 1
 LG_MAX_ATOMS, LG_MAX_TORSIONS, LG_MAX_SAMPLES = 256, 32, 1024
 
 EXPORTS = ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_sites", "lg_dock_stream", "lg_score",
-           "lg_refine", "lg_rank", "lg_autotune", "lg_valu_probe",
+           "lg_refine", "lg_rank", "lg_rank_static", "lg_autotune", "lg_valu_probe",
            "lg_set_tuning", "lg_get_tuning", "lg_bucket_stats", "lg_bucket_size", "lg_atom_clusters", "lg_rotamer_clusters",
            "lg_last_error", "lg_version")
 
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.lg_refine.argtypes = [c_void_p, P(lg_ligands), P(lg_refine_params), c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]
     lib.lg_rank.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.lg_rank_static.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.lg_autotune.argtypes = [c_void_p, P(lg_ligands), P(lg_dock_params), c_int32, P(lg_tuning),
                                 P(c_float), c_void_p]
     lib.lg_valu_probe.argtypes = [c_void_p, c_int32, c_int32, P(ctypes.c_double), c_void_p]
@@ -136,7 +137,8 @@ def load_library(path: str = LIB_PATH):
     lib.lg_rotamer_clusters.argtypes = [c_int32, c_int32, P(c_int32)]
     lib.lg_last_error.restype = ctypes.c_char_p
     for name in ("lg_load_pocket", "lg_free_pocket", "lg_dock_batch", "lg_dock_sites", "lg_dock_stream", "lg_score",
-                 "lg_refine", "lg_rank", "lg_autotune", "lg_valu_probe", "lg_set_tuning", "lg_get_tuning"):
+                 "lg_refine", "lg_rank", "lg_rank_static", "lg_autotune", "lg_valu_probe", "lg_set_tuning",
+                 "lg_get_tuning"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -480,6 +482,19 @@ def lg_rank(pocket: Pocket, score, group_size: int, top_m: int, stream=None):
     _check(_lib.lg_rank(pocket.handle, _ptr(score), ng, int(group_size), int(top_m), _ptr(res["top_idx"]),
                         _ptr(res["top_score"]), _ptr(res["top_member"]), _stream_handle(stream)))
     return res
+
+
+LG_RANK_STATIC_MAX_GROUPS, LG_RANK_STATIC_MAX_TOP = 1 << 20, 4096
+
+
+def lg_rank_static(score, group_size: int, top_m: int, top_idx, top_score, top_member=None, stream=None) -> None:
+    """lg_rank without a pocket and without any allocation (the library's fixed
+    device scratch): the caller passes the output tensors (top_idx int32
+    [top_m], top_score float32 [top_m], top_member int32 [top_m] or None), all
+    on the current device."""
+    ng = int(score.numel()) // int(group_size)
+    _check(_lib.lg_rank_static(_ptr(score), ng, int(group_size), int(top_m), _ptr(top_idx), _ptr(top_score),
+                               _ptr(top_member), _stream_handle(stream)))
 
 
 def docked_poses(ligs: DeviceLigands, out: dict) -> DeviceLigands:
