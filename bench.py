@@ -32,15 +32,24 @@ sys.path.insert(0, ROOT)
 
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: non-packed VALU issue, lane-ops/s
 
-# Algorithmic VALU lane-operations of the method, per unit of work (the op script
-# of the kernels: transform, nearest-voxel index, accumulate):
-OPS_ROT = 17      # per (rotation sample, atom)
-OPS_TRANS = 7     # per (translation sample, atom)
-OPS_TORS = 27     # per (torsion sample, moving atom)
-OPS_TMAT = 16     # per torsion sample: rotation matrix about the bond
-OPS_PAIR = 8      # per (moving, static) pair of the selected torsion sample
-OPS_PLACE = 15    # per atom per restart: placement
-OPS_TRI = 45      # per atom per restart: trilinear final score
+# VALU instructions per lane, per unit of work, in the inner loops of the docking
+# scans, counted in the gfx950 assembly of dock_bucket_kernel<1, 4> (four samples
+# per lane, loop control included): a loop pass of the rotation scan handles two
+# atoms x four samples in 107 (the lane's four quarter-turn samples share one 2-D
+# rotation), of the translation scan two atoms x four samples in 58, of the
+# torsion scan one moving atom x two samples in 58 plus 6 per two atoms; each
+# torsion sample's rotation matrix takes 13.  Placement and the final trilinear
+# score are counted from the op script (15 and 45 per atom and restart).
+ISA_ROT = 107 / 8        # per (rotation sample, atom)
+ISA_TRANS = 58 / 8       # per (translation sample, atom)
+ISA_TORS = 29 + 6 / 4    # per (torsion sample, moving atom)
+ISA_TMAT = 13            # per torsion sample
+OPS_PLACE = 15           # per atom per restart: placement
+OPS_TRI = 45             # per atom per restart: trilinear final score
+# The plain method's count: op-script constants per (sample, atom) of a rotation,
+# translation and torsion scan with its nearest lookup, and a pair test of every
+# (moving, static) atom pair for every torsion sample.
+PLAIN_ROT, PLAIN_TRANS, PLAIN_TORS, PLAIN_PAIR = 32, 23, 37, 8
 
 
 # Refinement, per pose and step (the op script of one step): per atom the trilinear
@@ -72,18 +81,37 @@ def refine_ops_per_step(L):
     return ops
 
 
-def algorithmic_ops(n_atoms, frag_sizes_per_lig, R, A, T, S):
-    """Lane-ops of docking each ligand (array over ligands).
-
-    frag_sizes_per_lig: list of arrays |F_k| per ligand."""
-    ops = np.zeros(len(n_atoms))
+def _per_ligand(n_atoms, frag_sizes_per_lig, fn):
+    out = np.zeros(len(n_atoms))
     for i, (N, F) in enumerate(zip(n_atoms, frag_sizes_per_lig)):
-        N = float(N)
-        mv = np.asarray(F, np.float64) - 1.0                 # moving atoms excluding the axis atom
-        per_sweep = (3 * A * N * OPS_ROT + 3 * T * N * OPS_TRANS + A * mv.sum() * OPS_TORS
-                     + len(F) * A * OPS_TMAT + (mv * (N - mv - 2)).sum() * OPS_PAIR)
-        ops[i] = R * (S * per_sweep + N * (OPS_PLACE + OPS_TRI))
-    return ops
+        out[i] = fn(float(N), np.asarray(F, np.float64) - 1.0)   # moving atoms of each torsion, axis atom excluded
+    return out
+
+
+def isa_ops(n_atoms, frag_sizes_per_lig, R, A, T, S):
+    """VALU lane-ops of docking each ligand: every sample of every scan at the
+    inner loops' per-unit instruction counts (a lower bound of what the kernel
+    issues: per-scan work and the tests of pairs that can clash are left out)."""
+    return _per_ligand(n_atoms, frag_sizes_per_lig, lambda N, mv: R * (
+        S * (3 * A * N * ISA_ROT + 3 * T * N * ISA_TRANS + A * mv.sum() * ISA_TORS + len(mv) * A * ISA_TMAT)
+        + N * (OPS_PLACE + OPS_TRI)))
+
+
+def plain_method_ops(n_atoms, frag_sizes_per_lig, R, A, T, S):
+    """Lane-ops of the plain method per ligand: op-script constants and a clash
+    test of every (moving, static) pair for every torsion sample."""
+    return _per_ligand(n_atoms, frag_sizes_per_lig, lambda N, mv: R * (
+        S * (3 * A * N * PLAIN_ROT + 3 * T * N * PLAIN_TRANS
+             + A * (mv.sum() * PLAIN_TORS + (mv * (N - mv - 2)).sum() * PLAIN_PAIR))
+        + N * (OPS_PLACE + OPS_TRI)))
+
+
+def lookups(n_atoms, frag_sizes_per_lig, R, A, T, S):
+    """Grid values read per ligand: one nearest-node value per (sample, moved
+    atom) of every scan, the current pose's atoms at each rotation and torsion
+    scan, eight per atom for the final trilinear score."""
+    return _per_ligand(n_atoms, frag_sizes_per_lig, lambda N, mv: R * (
+        S * (3 * A * N + 3 * T * N + A * mv.sum() + 3 * N + mv.sum()) + 8 * N))
 
 
 def frag_sizes(L):
@@ -110,10 +138,20 @@ def bucket_of(n_atoms, n_tors, tuning):
     return ca * nr + cr
 
 
-def read_traffic(kernel_tag):
-    """HBM traffic of one step's bucket launches from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+def kernel_tag(stat):
+    return f"dock_bucket_{stat['slots']}_{stat['samples_per_lane']}"
+
+
+def tuning_key(t):
+    """The tuning fields that shape the bucket launches, as one string."""
+    return (f"atoms {list(t.atom_bounds[:t.n_atom_clusters])} bonds {list(t.rot_bounds[:t.n_rot_clusters])} "
+            f"chunk {t.restart_chunk} scale {t.grid_scale} waves {list(t.waves_per_block)} lazy {t.lazy_clash}")
+
+
+def read_profile_value(name, field, tune_key):
+    """A figure of a committed rocprofv3 counter summary under profiles/, if it was
+    taken on the current kernel source and the same tuning (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -121,10 +159,10 @@ def read_traffic(kernel_tag):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != source_hash():
+    if kv.get("source_sha256") != source_hash() or kv.get("tuning") != tune_key:
         return None
     try:
-        return float(kv["hbm_bytes_per_dispatch"])
+        return float(kv[field])
     except (KeyError, ValueError):
         return None
 
@@ -350,6 +388,10 @@ def main():
     ap.add_argument("--autotune-ligands", type=int, default=16000,
                     help="tune the bucketed path on this many ligands before timing (0: default tuning); a "
                          "small sample favours fewer buckets, whose second launch it cannot fill")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON object of tuning fields (atom_bounds, rot_bounds, restart_chunk, grid_scale, "
+                         "waves_per_block, lazy_clash) to use instead of autotuning, e.g. to take counters on "
+                         "the tuning an earlier run chose")
     ap.add_argument("--refine-ligands", type=int, default=20000,
                     help="side run: refine the top --refine-poses poses of this many ligands (0: skip)")
     ap.add_argument("--refine-poses", type=int, default=64)
@@ -415,7 +457,22 @@ def main():
 
     # ---- autotuning on a prefix of the library (reported, not timed)
     tune = None
-    if args.autotune_ligands > 0:
+    if args.tuning:
+        spec = json.loads(args.tuning)
+        t = pocket.get_tuning()
+        t.n_atom_clusters = len(spec["atom_bounds"])
+        for c, b in enumerate(spec["atom_bounds"]):
+            t.atom_bounds[c] = b
+        t.n_rot_clusters = len(spec["rot_bounds"])
+        for c, b in enumerate(spec["rot_bounds"]):
+            t.rot_bounds[c] = b
+        for c, v in enumerate(spec["waves_per_block"]):
+            t.waves_per_block[c] = v
+        t.restart_chunk, t.grid_scale, t.lazy_clash = spec["restart_chunk"], spec["grid_scale"], spec["lazy_clash"]
+        pocket.set_tuning(t)
+        tune = dict(given=spec)
+        log(f"tuning given: {tuning_key(t)}")
+    elif args.autotune_ligands > 0:
         nt = min(args.autotune_ligands, n)
         Lt = L.subset(np.arange(nt))
         dlt = lg.device_ligands(Lt.atom_offset, Lt.tors_offset, Lt.x, Lt.y, Lt.z, Lt.frag_mask, Lt.tors_atoms,
@@ -428,6 +485,8 @@ def main():
                     atom_bounds=list(tt.atom_bounds[:tt.n_atom_clusters]),
                     rot_bounds=list(tt.rot_bounds[:tt.n_rot_clusters]))
         log(f"autotune on {nt} ligands: {tune}")
+        log("  as --tuning: " + json.dumps({k: tune[k] for k in ("atom_bounds", "rot_bounds", "restart_chunk",
+                                                                 "grid_scale", "waves_per_block", "lazy_clash")}))
         del dlt
     if args.experiment == "screen":
         print(json.dumps(experiment_screen(lg, torch, w, pocket, L, dl, rt, at, kw, max(args.stream_chunk, 1000),
@@ -459,46 +518,65 @@ def main():
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = n * args.steps / elapsed
 
-    # ---- per-kernel durations: one more step launched directly on the stream (no
-    # graph), with HIP events recorded on that stream between the bucket launches
+    # ---- per-kernel durations: a few more steps launched directly on the stream
+    # (no graph), the bucket launches one after another exactly as in the graph
+    # replays, with HIP events recorded on that stream between them
     tuning = pocket.get_tuning()
     eager = lg.lg_tuning.from_buffer_copy(tuning)
     eager.use_graph = 0
     pocket.set_tuning(eager)
-    out = dock(dl, lg.LG_BUCKETED, out)
-    torch.cuda.synchronize()
-    stats = pocket.bucket_stats()
-    for b in stats:
-        bucket_ms.setdefault(b["bucket"], []).append(b["ms"])
+    timing_steps = max(1, min(3, args.steps))
+    stats = []
+    direct_ms = []
+    for s in range(timing_steps):
+        out = dock(dl, lg.LG_BUCKETED, out)
+        torch.cuda.synchronize()
+        stats = pocket.bucket_stats()
+        for b in stats:
+            bucket_ms.setdefault(b["bucket"], []).append(b["ms"])
+        direct_ms.append(stats[0]["span_ms"] if stats else 0.0)
     pocket.set_tuning(tuning)
-    log("timing step (events between bucket launches) done")
+    log(f"timing steps (events between bucket launches) done: bucket launches {np.mean(direct_ms):.1f} ms "
+        f"per step against {ms_per_step:.1f} ms per graph-replayed step")
 
-    # ---- roofline of the dominant kernel: the bucket launch when one bucket holds
-    # every ligand; when several run concurrently, their launches taken together
-    # (first start to last end), since their durations overlap
+    # ---- roofline of the dominant kernel: the bucket launch that takes the most time
     bid = bucket_of(L.n_atoms, L.n_tors, tuning)
     fs = frag_sizes(L)
-    ops = algorithmic_ops(L.n_atoms, fs, w.restarts, w.angle_samples, T, w.sweeps)
+    ops = isa_ops(L.n_atoms, fs, w.restarts, w.angle_samples, T, w.sweeps)
+    plain_ops = plain_method_ops(L.n_atoms, fs, w.restarts, w.angle_samples, T, w.sweeps)
+    looks = lookups(L.n_atoms, fs, w.restarts, w.angle_samples, T, w.sweeps)
     busy = [b for b in stats if b["ligands"] > 0]
-    if len(busy) == 1:
-        dom = busy[0]
-        dom_ms = float(np.mean(bucket_ms[dom["bucket"]]))
-        dom_ops = float(ops[bid == dom["bucket"]].sum())
-        kernel = f"dock_bucket_kernel<{dom['slots']},{dom['samples_per_lane']}>"
-    else:
-        dom_ms = float(stats[0]["span_ms"])
-        dom_ops = float(ops.sum())
-        kernel = " + ".join(f"dock_bucket_kernel<{b['slots']},{b['samples_per_lane']}>" for b in busy) + " (concurrent)"
-    # HBM bytes of one step's bucket launches (all buckets), measured on this source
-    traffic = read_traffic(f"dock_buckets_{args.workload}")
+    dom = max(busy, key=lambda b: float(np.mean(bucket_ms[b["bucket"]])))
+    dom_ms = float(np.mean(bucket_ms[dom["bucket"]]))
+    sel = bid == dom["bucket"]
+    dom_ops, dom_plain, dom_looks = float(ops[sel].sum()), float(plain_ops[sel].sum()), float(looks[sel].sum())
+    kernel = f"dock_bucket_kernel<{dom['slots']},{dom['samples_per_lane']}>"
+    tune_key = tuning_key(tuning)
+    # HBM bytes and VALU issue of the dominant launch, from the committed rocprofv3
+    # counter summaries, when they were taken on this kernel source and tuning
+    traffic = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_traffic.txt", "hbm_bytes_per_dispatch",
+                                 tune_key)
+    valu_busy = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_valu.txt", "valu_busy", tune_key)
     achieved = dom_ops / (dom_ms * 1e-3)
     # the sustained non-packed v_fma_f32 rate on this device, beside the derived peak
     valu_meas = lg.lg_valu_probe(pocket, 0)
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(PEAK_LANE_OPS / 1e12, 3),
                     unit="TOP/s", frac=round(achieved / PEAK_LANE_OPS, 4), traffic=traffic, kernel=kernel,
-                    kernel_ms=round(dom_ms, 3), ligands_in_launch=int(sum(b["ligands"] for b in busy)),
-                    algorithmic_ops_per_launch=dom_ops, measured_valu_peak=round(valu_meas / 1e12, 3),
-                    frac_of_measured_peak=round(achieved / valu_meas, 4))
+                    kernel_ms=round(dom_ms, 3), ligands_in_launch=int(dom["ligands"]),
+                    ops_per_launch=dom_ops,
+                    ops_basis="VALU lane-ops of the scans' inner loops, every sample of every scan (gfx950 "
+                              "assembly count per unit; pair tests and per-scan work not counted)",
+                    valu_busy=valu_busy,
+                    gather_bw=round(4.0 * dom_looks / (dom_ms * 1e-3) / 1e9, 1), gather_unit="GB/s",
+                    measured_valu_peak=round(valu_meas / 1e12, 3),
+                    plain_method=dict(ops_per_launch=dom_plain,
+                                      rate=round(dom_plain / (dom_ms * 1e-3) / 1e12, 3),
+                                      ratio_to_peak=round(dom_plain / (dom_ms * 1e-3) / PEAK_LANE_OPS, 3),
+                                      basis="lane-ops the plain method would issue: op-script constants "
+                                            "32/23/37 per rotation/translation/torsion sample and atom, a "
+                                            "pair test (8) of every moving and static atom for every "
+                                            "torsion sample; a ratio above 1 is the speed-up of exact pair "
+                                            "pruning, not a hardware fraction"))
     total_ops = float(ops.sum())
 
     # ---- side runs: plain per-ligand launches, single-bucket ablation
@@ -661,14 +739,17 @@ def main():
         value=round(value, 2), unit="ligands/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(ms_per_step, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f32", data="synthetic",
-        config=dict(workload=f"{args.workload}: {n} ligands, atoms {w.nlo}-{w.nhi} (lognormal median 38), "
+        config=dict(workload=f"{args.workload}: {n} ligands, atoms {w.nlo}-{w.nhi}"
+                             f"{' (lognormal median 38)' if w.size_mode == 1 else ''}, "
                              f"bonds {w.klo}-{w.khi}, {w.grid_n}^3 grid @ {w.spacing} A, R={w.restarts}, "
                              f"A=T={w.angle_samples}, S={w.sweeps}, top-{w.top_k}",
                     ligands=n, restarts=w.restarts, angle_samples=w.angle_samples, sweeps=w.sweeps,
                     top_k=w.top_k, mode="bucketed persistent, one HIP graph"),
         roofline=roofline, cpu_baseline=cpu, autotune=tune,
-        algorithmic_top_s_whole_step=round(total_ops / (ms_per_step * 1e-3) / 1e12, 3),
-        speedup_vs_plain=round(value / side["plain"]["value"], 2) if "plain" in side else None,
+        isa_ops_rate_whole_step=round(total_ops / (ms_per_step * 1e-3) / 1e12, 3),
+        direct_launch_ms_per_step=round(float(np.mean(direct_ms)), 3),
+        speedup_vs_plain=(round(side["bucketed_same_prefix"]["value"] / side["plain"]["value"], 2)
+                          if "plain" in side else None),
         buckets=buckets, **side)
     print(json.dumps(rec), flush=True)
     pocket.free()

@@ -372,9 +372,8 @@ lg_status lg_autotune(lg_pocket pocket, const lg_ligands* ligands, const lg_dock
 /* Per-bucket report of the last LG_BUCKETED call on a handle -- the MI355X
  * analog of the paper's Table 1 (registers and resident blocks per size class)
  * plus durations when the call ran with use_graph = 0 (events around every
- * launch).  Bucket launches run concurrently (the first on the caller's stream,
- * the others on up to three library streams, joined before the top-k), largest
- * instance first, so their durations overlap; span_ms covers all of them.
+ * launch).  Bucket launches run one after another on the caller's stream,
+ * largest instance first, in both modes; span_ms covers all of them.
  * Fills up to `capacity` entries (NULL: none) and returns the number of bucket
  * launches, or a negative lg_status.  Synchronises the device to read ligand
  * counts and durations. */

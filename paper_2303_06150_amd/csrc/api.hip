@@ -113,22 +113,16 @@ struct lg_pocket_s {
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gkey;
   hipStream_t capture = nullptr;   // graphs are captured here, then launched on the caller's stream
-  // bucket launches after the first run concurrently on these streams (default
-  // priority), forked from and joined back into the launching stream
-  std::vector<hipStream_t> branches;
-  // per-bucket launches of the last call; timing events [0] fork, [1 + 2l] start
-  // and [2 + 2l] end of launch l, [1 + 2 nl] join; dependency-only events (fork,
-  // one per launch) for captured graphs
+  // per-bucket launches of the last call; timing events [0] before the first
+  // launch, [1 + 2l] start and [2 + 2l] end of launch l, [1 + 2 nl] after the last
   std::vector<lg_bucket_stat> launches;
   std::vector<hipEvent_t> events;
-  std::vector<hipEvent_t> deps;
   int32_t* counts_dev = nullptr;
   bool timed = false;
 };
 
 namespace {
 
-constexpr size_t kBranches = 3;   // with the launching stream: up to 4 buckets in flight
 
 
 lg_status ensure_ws(lg_pocket p, size_t bytes) {
@@ -294,9 +288,7 @@ lg_status lg_free_pocket(lg_pocket p) {
   (void)hipDeviceSynchronize();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->capture) (void)hipStreamDestroy(p->capture);
-  for (hipStream_t b : p->branches) (void)hipStreamDestroy(b);
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
-  for (hipEvent_t e : p->deps) (void)hipEventDestroy(e);
   if (p->ws) (void)hipFree(p->ws);
   if (p->padded) (void)hipFree(p->padded);
   if (p->brick) (void)hipFree(p->brick);
@@ -490,39 +482,24 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
       LG_HIP(hipEventCreate(&ev));
       p->events.push_back(ev);
     }
-    while (p->deps.size() < nl + 1) {
-      hipEvent_t ev;
-      LG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      p->deps.push_back(ev);
-    }
-    while (p->branches.size() < std::min<size_t>(nl > 0 ? nl - 1 : 0, kBranches)) {
-      hipStream_t b;
-      LG_HIP(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
-      p->branches.push_back(b);
-    }
     return LG_OK;
   };
-  // The whole bucketed sequence from stream `cs`: bucketing, then the bucket
-  // launches -- the first on cs, the others on the branch streams, all released
-  // by one fork event and joined back into cs -- then the top-k on cs.  Launches
-  // are ordered largest instance first, so the long items start early and the
-  // short ones fill the tails.  `timed`: events around every launch.
+  // The whole bucketed sequence on stream `cs`: bucketing, the bucket launches
+  // one after another, largest instance first, then the top-k.  `timed`: events
+  // around every launch.  (Launches on separate streams were tried: they overlap
+  // when launched directly but were slower than this sequence, and graph replays
+  // ran them one after another anyway.)
   auto enqueue = [&](const std::vector<lg_bucket_stat>& launches, hipStream_t cs, bool timed) -> hipError_t {
     const size_t nl = launches.size();
     hipError_t e = lg::launch_bucketing(L->atom_offset, L->tors_offset, n, cb, cls, counts, start, fill, perm, cursors, cs);
-    hipEvent_t fork = timed ? p->events[0] : p->deps[0];
-    if (e == hipSuccess) e = hipEventRecord(fork, cs);
+    if (e == hipSuccess && timed) e = hipEventRecord(p->events[0], cs);
     for (size_t l = 0; l < nl && e == hipSuccess; ++l) {
       const lg_bucket_stat& b = launches[l];
-      hipStream_t bs = (l == 0 || p->branches.empty()) ? cs : p->branches[(l - 1) % p->branches.size()];
-      if (l > 0) e = hipStreamWaitEvent(bs, fork, 0);
-      if (e == hipSuccess && timed) e = hipEventRecord(p->events[1 + 2 * l], bs);
+      if (timed) e = hipEventRecord(p->events[1 + 2 * l], cs);
       lg::QueueDev Q{perm, start, cursors, b.bucket, tu.restart_chunk};
-      if (e == hipSuccess) e = lg::launch_dock_bucket(b.slots, spl, b.waves_per_block, b.blocks, p->grid, Lg, D, Q, bs);
-      if (e == hipSuccess) e = hipEventRecord(timed ? p->events[2 + 2 * l] : p->deps[l], bs);
+      if (e == hipSuccess) e = lg::launch_dock_bucket(b.slots, spl, b.waves_per_block, b.blocks, p->grid, Lg, D, Q, cs);
+      if (e == hipSuccess && timed) e = hipEventRecord(p->events[2 + 2 * l], cs);
     }
-    for (size_t l = 1; l < nl && e == hipSuccess; ++l)
-      e = hipStreamWaitEvent(cs, timed ? p->events[2 + 2 * l] : p->deps[l], 0);
     if (e == hipSuccess && timed) e = hipEventRecord(p->events[1 + 2 * nl], cs);
     if (e == hipSuccess)
       e = lg::launch_topk(topk_slots, Lg, D, n, P->top_k, O->score, O->restart_id, O->x, O->y, O->z, O->all_scores,
