@@ -269,12 +269,35 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
   return j;
 }
 
+// 32-bit LDS address of a shared-memory pointer, and a float load from one.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p;
+}
+__device__ __forceinline__ float lds_load(uint32_t addr) {
+  return *(const __attribute__((address_space(3))) float*)(uintptr_t)addr;
+}
+
 // ---- rigid translation scan along lab axis E ---------------------------------
+// A translation moves an atom along E only, so its T samples read nodes of one
+// grid line: those between the nodes of the smallest and the largest
+// displacement (the node index is monotone in the displacement), span nodes at
+// most.  The wavefront reads each atom's run of nodes once -- 64 / span atoms
+// per gather instruction, into an LDS stage -- and every sample then takes its
+// value from the stage: the same value, node and sum order as a direct gather
+// per sample, with a fraction of the gather instructions.  Runs longer than a
+// wavefront (very wide translation ranges) fall back to direct gathers.
 template <int NSLOT, int SPL, int E>
-__device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr,
+__device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr, float* stage,
                           const SampleReg<SPL>& sm, const int* tab) {
   constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
   const int lane = lane_id();
+  const float cE = G.c0[E], ih = G.inv_h, fnE = G.fn[E];
+  // displacement delta * m of sample j (m = j, or j - T past T / 2) is monotone in
+  // m, so every sample's lies between those of the two extreme m
+  const int mlo = D.T >= 2 ? D.T / 2 - D.T : 0, mhi = D.T >= 2 ? D.T / 2 - 1 : 0;
+  const float da = D.delta * (float)mlo, db = D.delta * (float)mhi;
+  const float dmin = fminf(da, db), dmax = fmaxf(da, db);
+  int span = 0;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const int a = s * 64 + lane;
@@ -282,27 +305,71 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
       int ip = clamp_node(fmaf(p.x[P][s], G.inv_h, G.c0[P]), G.fn[P]);
       int iq = clamp_node(fmaf(p.x[Q][s], G.inv_h, G.c0[Q]), G.fn[Q]);
       const int part = boff(tab + G.tab_base[P] + 1, ip) + boff(tab + G.tab_base[Q] + 1, iq);
-      scr[a] = make_float4(p.x[E][s], __int_as_float(part), 0.f, 0.f);
+      const int lo = clamp_node(fmaf(p.x[E][s] + dmin, ih, cE), fnE);
+      const int hi = clamp_node(fmaf(p.x[E][s] + dmax, ih, cE), fnE);
+      span = max(span, hi - lo + 1);
+      scr[a] = make_float4(p.x[E][s], __int_as_float(part), __int_as_float(lo), 0.f);
     }
   }
+  span = wave_reduce_i32(span, OpMax());
   wave_sync();
   float acc[SPL];
 #pragma unroll
   for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
-  const float cE = G.c0[E], ih = G.inv_h, fnE = G.fn[E];
   const int* tE = tab + G.tab_base[E] + 1;
   const char* gk = G.gk;
-  auto gather = [&](int t, float (&out)[SPL]) {
-    const float4 d = scr[t];
-    const int part = __float_as_int(d.y);
+  if (span > 64) {
+    auto gather = [&](int t, float (&out)[SPL]) {
+      const float4 d = scr[t];
+      const int part = __float_as_int(d.y);
 #pragma unroll
-    for (int q = 0; q < SPL; ++q) {
-      float xe = d.x + sm.d[q];
-      int ie = clamp_node(fmaf(xe, ih, cE), fnE);
-      out[q] = grid_at(gk, part + boff(tE, ie));
+      for (int q = 0; q < SPL; ++q) {
+        float xe = d.x + sm.d[q];
+        int ie = clamp_node(fmaf(xe, ih, cE), fnE);
+        out[q] = grid_at(gk, part + boff(tE, ie));
+      }
+    };
+    pipelined_sum<SPL>(N, gather, acc);
+  } else {
+    const int per = 64 / span;               // atoms whose runs one gather instruction reads
+    const int tt = lane / span, ii = lane - tt * span;
+    const int imax = (int)fnE;
+    // lane (tt, ii): node lo + ii of atom g * per + tt (clamped into the grid;
+    // positions past an atom's own run are never read)
+    auto stage_load = [&](int g) {
+      const int t = g * per + tt;
+      float v = 0.f;
+      if (tt < per && t < N) {
+        const float4 d = scr[t];
+        v = grid_at(gk, __float_as_int(d.y) + boff(tE, min(__float_as_int(d.z) + ii, imax)));
+      }
+      return v;
+    };
+    const int groups = (N + per - 1) / per;
+    float next = stage_load(0);
+    for (int g = 0; g < groups; ++g) {
+      float* buf = stage + (g & 1) * 64;    // two buffers: this group's stage is written while
+      buf[lane] = next;                     // the previous group's reads are retired
+      wave_sync();
+      if (g + 1 < groups) next = stage_load(g + 1);
+      const int t0 = g * per, t1 = min(N, t0 + per);
+      for (int t = t0; t < t1; ++t) {
+        const float4 d = scr[t];
+        // LDS byte address of the atom's run, shifted so that node ie (in [lo, lo +
+        // span)) is at run + 4 ie
+        uint32_t run = lds_addr(buf) + 4u * (uint32_t)((t - t0) * span - __float_as_int(d.z));
+        asm volatile("" : "+v"(run));   // one base per atom: each sample then adds 4 ie in one shift-add
+        int ie[SPL];
+        float v[SPL];
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) ie[q] = clamp_node(fmaf(d.x + sm.d[q], ih, cE), fnE);
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) v[q] = lds_load(run + 4u * (uint32_t)ie[q]);
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) acc[q] += v[q];
+      }
     }
-  };
-  pipelined_sum<SPL>(N, gather, acc);
+  }
   const int j = wave_argmax(acc, sm.valid_t);
   apply_trans<NSLOT, E>(D, p, j);
   wave_sync();
@@ -589,9 +656,10 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
     int jr0 = rot_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm, tab);
     int jr1 = rot_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm, tab);
     int jr2 = rot_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm, tab);
-    int jt0 = trans_scan<NSLOT, SPL, 0>(G, D, p, N, scr, sm, tab);
-    int jt1 = trans_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm, tab);
-    int jt2 = trans_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm, tab);
+    float* stage = reinterpret_cast<float*>(cand);
+    int jt0 = trans_scan<NSLOT, SPL, 0>(G, D, p, N, scr, stage, sm, tab);
+    int jt1 = trans_scan<NSLOT, SPL, 1>(G, D, p, N, scr, stage, sm, tab);
+    int jt2 = trans_scan<NSLOT, SPL, 2>(G, D, p, N, scr, stage, sm, tab);
     int16_t* trow = tr ? tr + (size_t)sw * D.trace_w : nullptr;
     uint16_t* mrow = mrec + (size_t)sw * (6 + L.K);
     if (lane == 0) {
