@@ -283,7 +283,10 @@ lg_status lg_score(lg_pocket pocket, const lg_ligands* poses, int32_t interp, co
  * axis atoms, closer than sqrt(clash_dist2)) is rejected, the pose kept and
  * the step scale of later steps halved.  The best-scoring pose seen (including
  * the input) is written to x/y/z_out in the layout of the input coordinates,
- * its score to score_out [n*k].  One wavefront refines one pose. */
+ * its score to score_out [n*k].  One wavefront refines one pose; with k >= 2,
+ * ligands of at most 32 atoms are refined two poses per wavefront (same
+ * arithmetic per pose).  When the batch mixes size classes the call reads the
+ * class counts back, which synchronises `stream`. */
 typedef struct {
   int32_t steps;
   float eta_t, eta_w, eta_th;
@@ -405,8 +408,10 @@ int64_t lg_bucket_size(int64_t blocks_per_unit, int64_t units, int64_t threads_p
  * handle's device -- eight independent chains per lane, eight wavefronts per
  * SIMD, `iters` iterations, timed with events on `stream` after one warm-up
  * launch.  kind: 0 v_fma_f32, 1 v_add_f32, 2 v_add_u32, 3 v_med3_f32,
- * 4 v_mad_i32_i24.  Allocates and frees a small buffer; synchronises
- * `stream`. */
+ * 4 v_mad_i32_i24, 5 v_fma_f32 and v_add_u32 chains interleaved, 6 the
+ * nearest-node index sequence of a scan sample (add, fma, med3, floor
+ * conversion, shift-add, three-way add, and, conversion, add: ten operations).
+ * Allocates and frees a small buffer; synchronises `stream`. */
 lg_status lg_valu_probe(lg_pocket pocket, int32_t kind, int32_t iters, double* lane_ops_per_s, void* stream);
 
 /* Cluster boundaries (Sec. 3): atom clusters at multiples of the wavefront

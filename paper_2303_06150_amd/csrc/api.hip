@@ -42,6 +42,7 @@ hipError_t launch_bucketing(const int32_t* atom_offset, const int32_t* tors_offs
                             int32_t* cls, int32_t* counts, int32_t* start, int32_t* fill, int32_t* perm,
                             int32_t* cursors, hipStream_t st);
 hipError_t launch_refine(int nslot, const GridDev& G, const LigDev& P, const RefineDev& Rp, int n, hipStream_t st);
+hipError_t launch_refine_pair(const GridDev& G, const LigDev& P, const RefineDev& Rp, int n_lig, hipStream_t st);
 hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, const float* moves, int n, float* score,
                               float* grad, hipStream_t st);
 hipError_t launch_check(const int32_t* atom_offset, const int32_t* tors_offset, const int32_t* tors_atoms, int n,
@@ -1157,17 +1158,26 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
   hipStream_t st = (hipStream_t)stream;
   LG_HIP(hipSetDevice(p->device));
   const int n = L->n;
+  // size classes: ligands of at most 32 atoms and 31 bonds with two or more
+  // poses each are refined two poses per wavefront (a half-wavefront has a lane
+  // per bond and one for the rigid rotation); the others by the instance with
+  // one atom slot per 64 atoms.  Class (atom class c, bond class r) is bucket
+  // c * nr + r.
+  const bool pairs = rp->poses_per_ligand >= 2;
   lg::ClusterBounds cb;
   std::memset(&cb, 0, sizeof cb);
-  cb.na = LG_MAX_ATOMS / 64;   // one size class per kernel instance (atom slots)
-  for (int c = 0; c < cb.na; ++c) cb.atom[c] = 64 * (c + 1);
-  cb.nr = 1;
-  cb.rot[0] = LG_MAX_TORSIONS;
+  cb.na = 0;
+  if (pairs) cb.atom[cb.na++] = 32;
+  for (int c = 0; c < LG_MAX_ATOMS / 64; ++c) cb.atom[cb.na++] = 64 * (c + 1);
+  cb.nr = pairs ? 2 : 1;
+  cb.rot[0] = pairs ? LG_MAX_TORSIONS - 1 : LG_MAX_TORSIONS;
+  cb.rot[1] = LG_MAX_TORSIONS;
+  const int nb = cb.na * cb.nr;
   Layout lay;
   const size_t o_stats = lay.take(16 * sizeof(int32_t));
   const size_t o_cls = lay.take((size_t)n * sizeof(int32_t));
   const size_t o_perm = lay.take((size_t)n * sizeof(int32_t));
-  const size_t o_cnt = lay.take((size_t)(4 * cb.na + 1) * sizeof(int32_t));
+  const size_t o_cnt = lay.take((size_t)(4 * nb + 1) * sizeof(int32_t));
   s = ensure_ws(p, lay.off);
   if (s != LG_OK) return s;
   char* ws = (char*)p->ws;
@@ -1186,7 +1196,11 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
   R.clash2 = rp->clash_dist2;
   R.xo = x_out; R.yo = y_out; R.zo = z_out; R.score = score_out;
   const int kpl = rp->poses_per_ligand;
-  if (max_atoms <= 64) {
+  if (pairs && max_atoms <= 32 && max_tors >= 0 && max_tors < LG_MAX_TORSIONS) {
+    LG_HIP(lg::launch_refine_pair(p->grid, lig_dev(L), R, n, st));
+    return LG_OK;
+  }
+  if (!pairs && max_atoms <= 64) {
     LG_HIP(lg::launch_refine(1, p->grid, lig_dev(L), R, n * kpl, st));
     return LG_OK;
   }
@@ -1194,25 +1208,29 @@ lg_status lg_refine(lg_pocket p, const lg_ligands* L, const lg_refine_params* rp
   int32_t* cls = (int32_t*)(ws + o_cls);
   int32_t* perm = (int32_t*)(ws + o_perm);
   int32_t* counts = (int32_t*)(ws + o_cnt);
-  int32_t* start = counts + cb.na;
-  int32_t* fill = start + cb.na + 1;
-  int32_t* cursors = fill + cb.na;
+  int32_t* start = counts + nb;
+  int32_t* fill = start + nb + 1;
+  int32_t* cursors = fill + nb;
   LG_HIP(lg::launch_bucketing(L->atom_offset, L->tors_offset, n, cb, cls, counts, start, fill, perm, cursors, st));
-  int32_t hs[LG_MAX_ATOMS / 64 + 1];
-  LG_HIP(hipMemcpyAsync(hs, start, sizeof hs, hipMemcpyDeviceToHost, st));
+  int32_t hs[2 * (LG_MAX_ATOMS / 64 + 1) + 1];
+  LG_HIP(hipMemcpyAsync(hs, start, (size_t)(nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   LG_HIP(hipStreamSynchronize(st));
-  for (int c = 0; c < cb.na; ++c) {
-    const int cnt = hs[c + 1] - hs[c];
+  for (int b = 0; b < nb; ++b) {
+    const int cnt = hs[b + 1] - hs[b];
     if (cnt <= 0) continue;
-    R.lig_ids = perm + hs[c];
-    LG_HIP(lg::launch_refine(c + 1, p->grid, lig_dev(L), R, cnt * kpl, st));
+    const int c = b / cb.nr, r = b % cb.nr;
+    R.lig_ids = perm + hs[b];
+    if (pairs && c == 0 && r == 0)
+      LG_HIP(lg::launch_refine_pair(p->grid, lig_dev(L), R, cnt, st));
+    else
+      LG_HIP(lg::launch_refine((cb.atom[c] + 63) / 64, p->grid, lig_dev(L), R, cnt * kpl, st));
   }
   return LG_OK;
 }
 
 lg_status lg_valu_probe(lg_pocket p, int32_t kind, int32_t iters, double* lane_ops_per_s, void* stream) {
   if (!p || !lane_ops_per_s) return fail(LG_ERR_INVALID_ARG, "pocket and lane_ops_per_s must not be NULL");
-  if (kind < 0 || kind > 4) return fail(LG_ERR_INVALID_ARG, "kind %d outside 0..4", kind);
+  if (kind < 0 || kind > 6) return fail(LG_ERR_INVALID_ARG, "kind %d outside 0..6", kind);
   if (iters < 1 || iters > 1000000) return fail(LG_ERR_LIMIT, "iters %d outside 1..1000000", iters);
   hipStream_t st = (hipStream_t)stream;
   LG_HIP(hipSetDevice(p->device));
@@ -1236,7 +1254,8 @@ lg_status lg_valu_probe(lg_pocket p, int32_t kind, int32_t iters, double* lane_o
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(out);
   if (e != hipSuccess) return fail(LG_ERR_DEVICE, "probe failed: %s", hipGetErrorString(e));
-  *lane_ops_per_s = 8.0 * iters * (double)blocks * 256.0 / (ms * 1e-3);
+  const double ops_per_iter = kind == 6 ? 80.0 : 8.0;   // kind 6: ten VALU operations per chain step
+  *lane_ops_per_s = ops_per_iter * iters * (double)blocks * 256.0 / (ms * 1e-3);
   return LG_OK;
 }
 

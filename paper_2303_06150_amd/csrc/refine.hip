@@ -567,6 +567,387 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
   if (lane == 0) Rp.score[i] = best_s;
 }
 
+// ---- two poses per wavefront (ligands of at most 32 atoms) -------------------
+// Poses 2m and 2m + 1 of one ligand share a wavefront: pose h = lane / 32 in
+// lanes 32 h .. 32 h + 31, atom a in lane 32 h + a.  Both halves have the same
+// atoms, bonds and fragment masks, so every loop bound and branch is the
+// ligand's and the halves run one control flow; per-pose values (pivot, step,
+// step scale, accept) are per lane.  Each half does exactly the arithmetic of
+// refine_kernel<1> for its pose: the same sums in atom order, the same step
+// script, the same clash rule.  A wavefront without a second pose (odd k)
+// refines the first pose twice and stores it once.
+constexpr int PAIR_STRIDE = 36;                              // 32 atoms + pad, 16-byte aligned columns
+constexpr int PAIR_TILE_FLOATS = TILE_COLS * PAIR_STRIDE;    // per half
+constexpr int PAIR_POS_FLOAT4 = 48;                          // 32 atoms + the clash pass's wrap copy
+static_assert(PAIR_TILE_FLOATS / 4 >= 3 * 32, "the matrices of 31 bonds and the rigid move fit in a half's tile");
+// LDS of one wavefront in float4: poses, tiles, bond atoms, 1/lengths, steps,
+// bond gradients, gradient results
+constexpr int pair_wave_float4() {
+  return 2 * PAIR_POS_FLOAT4 + 2 * PAIR_TILE_FLOATS / 4 + 16 + 8 + 2 * 8 + 2 * 8 + 2 * GRAD_RES_FLOATS / 4;
+}
+
+__device__ __forceinline__ int half_of_lane() { return lane_id() >> 5; }
+
+// Sum over atoms 0..N-1 of each half in atom order; every lane gets its half's.
+__device__ __forceinline__ float pair_atom_order_sum(float v, int N) {
+  float a = 0.f, b = 0.f;
+  for (int l = 0; l < N; ++l) {
+    a = a + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+    b = b + __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + l));
+  }
+  return half_of_lane() ? b : a;
+}
+
+struct PairPose {
+  float x[3];
+  float piv[3];
+};
+
+// move_gradient for the two halves: columns per half in that half's tile, summed
+// in atom order by lanes 32 h + c; results in that half's res.
+__device__ float pair_move_gradient(const GridDev& G, const PairPose& p, uint32_t mk, int N, int K, const int2* tors,
+                                    const float4* pos_h, const LaneAxis& ax, float (&g_out)[6], float* thg_h,
+                                    float* tile_h, float* res_h) {
+  const int la = lane_id() & 31;
+  float gg[3] = {0.f, 0.f, 0.f};
+  const float v = la < N ? trilinear(G, p.x[0], p.x[1], p.x[2], gg) : 0.f;
+  for (int k0 = 0, first = 1; first || k0 < K; first = 0) {
+    const int base = first ? 7 : 0;
+    const int nb = min(K - k0, (TILE_COLS - base) / 3);
+    const int ncol = base + 3 * nb;
+    const int col0 = first ? 0 : 7 + 3 * k0;
+    if (first) {
+      const float r0 = p.x[0] - p.piv[0], r1 = p.x[1] - p.piv[1], r2 = p.x[2] - p.piv[2];
+      tile_h[0 * PAIR_STRIDE + la] = v;
+      tile_h[1 * PAIR_STRIDE + la] = gg[0];
+      tile_h[2 * PAIR_STRIDE + la] = gg[1];
+      tile_h[3 * PAIR_STRIDE + la] = gg[2];
+      tile_h[4 * PAIR_STRIDE + la] = r1 * gg[2] - r2 * gg[1];
+      tile_h[5 * PAIR_STRIDE + la] = r2 * gg[0] - r0 * gg[2];
+      tile_h[6 * PAIR_STRIDE + la] = r0 * gg[1] - r1 * gg[0];
+    }
+    for (int kk = 0; kk < nb; ++kk) {
+      const int k = k0 + kk;
+      const float4 pa = pos_h[tors[k].x];   // pivot atom a_k of this half's pose
+      const bool in = (mk >> k) & 1u;
+      const float r0 = p.x[0] - pa.x, r1 = p.x[1] - pa.y, r2 = p.x[2] - pa.z;
+      float* t = tile_h + (base + 3 * kk) * PAIR_STRIDE + la;
+      t[0] = in ? r1 * gg[2] - r2 * gg[1] : 0.f;
+      t[PAIR_STRIDE] = in ? r2 * gg[0] - r0 * gg[2] : 0.f;
+      t[2 * PAIR_STRIDE] = in ? r0 * gg[1] - r1 * gg[0] : 0.f;
+    }
+    wave_sync();
+    float acc = 0.f;
+    if (la < ncol) {
+      const float* col = tile_h + la * PAIR_STRIDE;
+      int l = 0;
+      for (; l + 4 <= N; l += 4) {
+        const float4 q4 = *reinterpret_cast<const float4*>(col + l);
+        acc = acc + q4.x;
+        acc = acc + q4.y;
+        acc = acc + q4.z;
+        acc = acc + q4.w;
+      }
+      for (; l < N; ++l) acc = acc + col[l];
+    }
+    wave_sync();
+    if (la < ncol) res_h[col0 + la] = acc;
+    k0 += nb;
+  }
+  wave_sync();
+#pragma unroll
+  for (int d = 0; d < 6; ++d) g_out[d] = res_h[1 + d];
+  if (la < K) {
+    const float* t = res_h + 7 + 3 * la;
+    thg_h[la] = ax.ux * t[0] + ax.uy * t[1] + ax.uz * t[2];
+  }
+  return res_h[0];
+}
+
+// Clash rule of refinement for both halves (as move_clash_free, atom i of each
+// half against atoms i + d of its own pose): the result of the lane's half.  The
+// pass stops once both halves have found a clash.
+__device__ bool pair_clash_free(const PairPose& p, uint32_t mk, int N, const int2* tors, const float4* pos_h,
+                                float clash2) {
+  const int la = lane_id() & 31;
+  const uint64_t lo_half = 0x00000000FFFFFFFFull, hi_half = ~lo_half;
+  auto both = [&](uint64_t b) { return (b & lo_half) != 0ull && (b & hi_half) != 0ull; };
+  bool clash = false;
+  const int half = N >> 1;
+  const int full = (N - 1) >> 1;
+  if (la < N) {
+    const float4* pi = pos_h + la;
+    const float xi = p.x[0], yi = p.x[1], zi = p.x[2];
+    auto near = [&](const float4& pj) {
+      const float dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+      return fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < clash2;
+    };
+    auto rule = [&](int d, const float4& pj) {
+      const int j = la + d >= N ? la + d - N : la + d;
+      clash |= pair_changes(mk, __float_as_uint(pj.w), la, j, tors);
+    };
+    auto test = [&](int d) {
+      const float4 pj = pi[d];
+      const bool n0 = near(pj);
+      if (__ballot(n0) != 0ull && n0) rule(d, pj);
+    };
+    int d = 1;
+    for (; d + 3 <= full; d += 4) {
+      const float4 p0 = pi[d], p1 = pi[d + 1], p2 = pi[d + 2], p3 = pi[d + 3];
+      const bool n0 = near(p0), n1 = near(p1), n2 = near(p2), n3 = near(p3);
+      if (__ballot(n0 || n1 || n2 || n3) != 0ull) {
+        if (n0) rule(d, p0);
+        if (n1) rule(d + 1, p1);
+        if (n2) rule(d + 2, p2);
+        if (n3) rule(d + 3, p3);
+        if (both(__ballot(clash))) break;
+      }
+    }
+    if (!both(__ballot(clash))) {
+      for (; d <= full; ++d) test(d);
+      if (half > full && la < half) test(half);
+    }
+  }
+  const uint64_t b = __ballot(clash);
+  return (b & (half_of_lane() ? hi_half : lo_half)) == 0ull;
+}
+
+__device__ __forceinline__ void pair_store_pose(float4* pos_h, const PairPose& p, uint32_t mk, int N, bool wrap) {
+  const int la = lane_id() & 31;
+  const int full = (N - 1) >> 1;
+  const float4 v = make_float4(p.x[0], p.x[1], p.x[2], __uint_as_float(mk));
+  if (la < N) pos_h[la] = v;
+  if (wrap && la < full) pos_h[N + la] = v;
+}
+
+__global__ __launch_bounds__(256) void refine_pair_kernel(GridDev G, LigDev P, RefineDev Rp, int n_pairs) {
+  extern __shared__ float4 lds[];
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6, lane = lane_id();
+  const int h = lane >> 5, la = lane & 31;
+  float4* base4 = lds + (size_t)wave * pair_wave_float4();
+  float4* pos_h = base4 + h * PAIR_POS_FLOAT4;
+  float* tile_h = reinterpret_cast<float*>(base4 + 2 * PAIR_POS_FLOAT4) + h * PAIR_TILE_FLOATS;
+  int2* tors = reinterpret_cast<int2*>(base4 + 2 * PAIR_POS_FLOAT4 + 2 * PAIR_TILE_FLOATS / 4);   // 32 entries
+  float* inv_len = reinterpret_cast<float*>(tors + 32);                                          // 32 entries
+  float* th_h = inv_len + 32 + h * 32;        // bond steps of this half's pose
+  float* thg_h = inv_len + 96 + h * 32;       // bond gradients
+  float* res_h = inv_len + 160 + h * GRAD_RES_FLOATS;
+  const int w = blockIdx.x * nwaves + wave;   // pair w: members 2m, 2m + 1 of ligand w / ppl
+  if (w >= n_pairs) return;
+  const int ppl = (Rp.kpl + 1) >> 1;
+  const int li = w / ppl, m = w - li * ppl;
+  const int lig = Rp.lig_ids ? __builtin_amdgcn_readfirstlane(Rp.lig_ids[li]) : li;
+  const bool second = 2 * m + 1 < Rp.kpl;     // the wavefront has two poses
+  const int member = 2 * m + (second ? h : 0);
+  const bool writer = h == 0 || second;
+  const int i = lig * Rp.kpl + member;        // pose index in the caller's layout
+  const int abase = __builtin_amdgcn_readfirstlane(P.atom_offset[lig]);
+  const int N = __builtin_amdgcn_readfirstlane(P.atom_offset[lig + 1]) - abase;
+  const int toff = __builtin_amdgcn_readfirstlane(P.tors_offset[lig]);
+  const int K = __builtin_amdgcn_readfirstlane(P.tors_offset[lig + 1]) - toff;
+  const size_t cbase = (size_t)Rp.kpl * abase + (size_t)member * N;   // coordinates of the lane's pose
+  if (lane < K) {
+    tors[lane] = make_int2(P.tors_atoms[2 * (toff + lane)], P.tors_atoms[2 * (toff + lane) + 1]);
+    inv_len[lane] = P.inv_len[toff + lane];
+  }
+  const bool table = axes_fixed_under_torsions(P, abase, toff, K);
+  const bool in = la < N;
+  PairPose cur, best;
+  cur.x[0] = in ? P.x[cbase + la] : 0.f;
+  cur.x[1] = in ? P.y[cbase + la] : 0.f;
+  cur.x[2] = in ? P.z[cbase + la] : 0.f;
+  const uint32_t mk = in ? P.mask[abase + la] : 0u;
+  uint32_t mv = mk;   // bonds that rotate the lane's atom (b_k excluded)
+  for (int k = 0; k < K; ++k) {
+    const int b = __builtin_amdgcn_readfirstlane(P.tors_atoms[2 * (toff + k) + 1]);
+    if (la == b) mv &= ~(1u << k);
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cur.piv[d] = P.ref[3 * (size_t)i + d];
+  wave_sync();
+  best = cur;
+  float v = in ? trilinear(G, cur.x[0], cur.x[1], cur.x[2], nullptr) : 0.f;
+  float best_s = pair_atom_order_sum(v, N);
+  float scale = 1.f;
+  float g[6];
+  LaneAxis ax{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool fresh = true, pending = false;   // per half, as in refine_kernel
+  pair_store_pose(pos_h, cur, mk, N, false);
+  wave_sync();
+  for (int step = 0; step < Rp.steps; ++step) {
+    if (wave_any(fresh)) {
+      // both halves take the gradient of their current pose; a half whose pose
+      // did not change gets the values it already had
+      if (la < K) {
+        const int2 t = tors[la];
+        const float4 pa = pos_h[t.x], pb = pos_h[t.y];
+        const float il = inv_len[la];
+        ax = LaneAxis{pa.x, pa.y, pa.z, (pb.x - pa.x) * il, (pb.y - pa.y) * il, (pb.z - pa.z) * il};
+      }
+      const float sc = pair_move_gradient(G, cur, mk, N, K, tors, pos_h, ax, g, thg_h, tile_h, res_h);
+      wave_sync();
+      if (pending && sc > best_s) {
+        best_s = sc;
+        best = cur;
+      }
+      fresh = pending = false;
+    }
+    float q[6];
+    float dt[3], dw[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { dt[d] = Rp.eta_t * g[d]; dw[d] = Rp.eta_w * g[3 + d]; }
+    // clip factors: lane 32 h the translation's, lane 32 h + 1 the rotation's
+    float ft, fw;
+    {
+      const bool rot = la == 1;
+      const float a0 = rot ? dw[0] : dt[0], a1 = rot ? dw[1] : dt[1], a2 = rot ? dw[2] : dt[2];
+      const float clip = rot ? Rp.clip_w : Rp.clip_t;
+      const float nrm = sqrtf(fmaf(a2, a2, fmaf(a1, a1, a0 * a0)));
+      const float f = nrm > clip ? clip / nrm : 1.f;
+      const float f0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f), 0));
+      const float f1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f), 1));
+      const float f32 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f), 32));
+      const float f33 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f), 33));
+      ft = h ? f32 : f0;
+      fw = h ? f33 : f1;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      q[d] = (dt[d] * ft) * scale;
+      q[3 + d] = (dw[d] * fw) * scale;
+    }
+    float thk = 0.f;
+    if (la < K) {
+      float t = Rp.eta_th * thg_h[la];
+      t = fminf(fmaxf(t, -Rp.clip_th), Rp.clip_th);
+      thk = t * scale;
+      th_h[la] = thk;
+    }
+    PairPose cand = cur;
+    const float w2 = fmaf(q[5], q[5], fmaf(q[4], q[4], q[3] * q[3]));
+    const bool rot = w2 > 0.f;
+    if (table) {
+      // lane 32 h + k < K: bond k's matrix of pose h; lane 32 h + K: the rigid rotation's
+      float4* mats = reinterpret_cast<float4*>(tile_h);
+      float w = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+      if (rot) {
+        w = sqrtf(w2);
+        wx = q[3] / w;
+        wy = q[4] / w;
+        wz = q[5] / w;
+      }
+      const bool bond = la < K && thk != 0.f;
+      if (bond || (la == K && rot)) {
+        const float ang = bond ? thk : w;
+        const float ux = bond ? ax.ux : wx, uy = bond ? ax.uy : wy, uz = bond ? ax.uz : wz;
+        float c, sn, mm[9];
+        step_cos_sin(ang, c, sn);
+        torsion_matrix(ux, uy, uz, c, sn, mm);
+        mats[3 * la] = make_float4(mm[0], mm[1], mm[2], ax.xa);
+        mats[3 * la + 1] = make_float4(mm[3], mm[4], mm[5], ax.ya);
+        mats[3 * la + 2] = make_float4(mm[6], mm[7], mm[8], ax.za);
+      }
+      wave_sync();
+      for (int k = K - 1; k >= 0; --k) {
+        const float ang = th_h[k];
+        if (!wave_any(ang != 0.f)) continue;
+        if (ang != 0.f && ((mv >> k) & 1u)) {
+          const float4 r0 = mats[3 * k], r1 = mats[3 * k + 1], r2 = mats[3 * k + 2];
+          const float mm[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
+          float y0, y1, y2;
+          mat_apply(mm, cand.x[0] - r0.w, cand.x[1] - r1.w, cand.x[2] - r2.w, y0, y1, y2);
+          cand.x[0] = r0.w + y0;
+          cand.x[1] = r1.w + y1;
+          cand.x[2] = r2.w + y2;
+        }
+      }
+      if (rot) {
+        const float4 r0 = mats[3 * K], r1 = mats[3 * K + 1], r2 = mats[3 * K + 2];
+        const float mm[9] = {r0.x, r0.y, r0.z, r1.x, r1.y, r1.z, r2.x, r2.y, r2.z};
+        float y0, y1, y2;
+        mat_apply(mm, cand.x[0] - cand.piv[0], cand.x[1] - cand.piv[1], cand.x[2] - cand.piv[2], y0, y1, y2);
+        cand.x[0] = cand.piv[0] + y0;
+        cand.x[1] = cand.piv[1] + y1;
+        cand.x[2] = cand.piv[2] + y2;
+      }
+    } else {
+      // bond axes as they stand when each torsion is applied (reverse order), from
+      // the lane's own half
+      wave_sync();
+      for (int k = K - 1; k >= 0; --k) {
+        const float ang = th_h[k];
+        if (!wave_any(ang != 0.f)) continue;
+        float c, sn;
+        step_cos_sin(ang, c, sn);
+        const int a = tors[k].x, b = tors[k].y;
+        auto pick = [&](float val, int atom) {
+          const float v0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(val), atom));
+          const float v1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(val), 32 + atom));
+          return h ? v1 : v0;
+        };
+        const float xa = pick(cand.x[0], a), ya = pick(cand.x[1], a), za = pick(cand.x[2], a);
+        const float il = inv_len[k];
+        const float ux = (pick(cand.x[0], b) - xa) * il, uy = (pick(cand.x[1], b) - ya) * il,
+                    uz = (pick(cand.x[2], b) - za) * il;
+        float mm[9];
+        torsion_matrix(ux, uy, uz, c, sn, mm);
+        if (ang != 0.f && ((mv >> k) & 1u)) {
+          float y0, y1, y2;
+          mat_apply(mm, cand.x[0] - xa, cand.x[1] - ya, cand.x[2] - za, y0, y1, y2);
+          cand.x[0] = xa + y0;
+          cand.x[1] = ya + y1;
+          cand.x[2] = za + y2;
+        }
+      }
+      if (rot) {
+        const float w = sqrtf(w2);
+        float c, sn, mm[9];
+        step_cos_sin(w, c, sn);
+        torsion_matrix(q[3] / w, q[4] / w, q[5] / w, c, sn, mm);
+        float y0, y1, y2;
+        mat_apply(mm, cand.x[0] - cand.piv[0], cand.x[1] - cand.piv[1], cand.x[2] - cand.piv[2], y0, y1, y2);
+        cand.x[0] = cand.piv[0] + y0;
+        cand.x[1] = cand.piv[1] + y1;
+        cand.x[2] = cand.piv[2] + y2;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      cand.x[d] = cand.x[d] + q[d];
+      cand.piv[d] = cand.piv[d] + q[d];
+    }
+    wave_sync();
+    pair_store_pose(pos_h, cand, mk, N, true);
+    wave_sync();
+    const bool ok = pair_clash_free(cand, mk, N, tors, pos_h, Rp.clash2);
+    wave_sync();
+    if (!ok) {
+      scale = scale * 0.5f;
+      pair_store_pose(pos_h, cur, mk, N, false);   // pos holds the current pose whenever a gradient is due
+    } else {
+      cur = cand;
+      fresh = pending = true;
+    }
+    wave_sync();
+  }
+  if (wave_any(pending)) {
+    v = in ? trilinear(G, cur.x[0], cur.x[1], cur.x[2], nullptr) : 0.f;
+    const float sc = pair_atom_order_sum(v, N);
+    if (pending && sc > best_s) {
+      best_s = sc;
+      best = cur;
+    }
+  }
+  if (writer) {
+    if (in) {
+      Rp.xo[cbase + la] = best.x[0];
+      Rp.yo[cbase + la] = best.x[1];
+      Rp.zo[cbase + la] = best.x[2];
+    }
+    if (la == 0) Rp.score[i] = best_s;
+  }
+}
+
 // Score of poses moved by given local parameters, and the gradient with respect
 // to those parameters: each pose i is moved by q_i = (t, w, theta) (layout of
 // lg_score's gradient: 6 i + tors_offset[i]), scored (trilinear, atom order) and
@@ -669,6 +1050,18 @@ hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, cons
 }
 
 static size_t refine_lds(int nslot, int wpb) { return (size_t)wpb * refine_wave_float4(nslot) * sizeof(float4); }
+
+// Two poses per wavefront for ligands of at most 32 atoms: n_lig ligands of the
+// launch (Rp.lig_ids, or 0..n_lig-1), ceil(kpl / 2) wavefronts each.
+hipError_t launch_refine_pair(const GridDev& G, const LigDev& P, const RefineDev& Rp, int n_lig, hipStream_t st) {
+  const long long waves = (long long)n_lig * ((Rp.kpl + 1) / 2);
+  if (waves == 0) return hipSuccess;
+  const int wpb = 4;
+  const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
+  const size_t lds = (size_t)wpb * pair_wave_float4() * sizeof(float4);
+  hipLaunchKernelGGL(refine_pair_kernel, grid, block, lds, st, G, P, Rp, (int)waves);
+  return hipGetLastError();
+}
 
 hipError_t launch_refine(int nslot, const GridDev& G, const LigDev& P, const RefineDev& Rp, int n, hipStream_t st) {
   if (n == 0) return hipSuccess;

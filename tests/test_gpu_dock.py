@@ -363,6 +363,47 @@ def test_dock_refine_rank_pipeline(lgmod, tiny):
 
 
 
+def test_refine_two_poses_per_wavefront(lgmod, tiny):
+    """Ligands of at most 32 atoms with k >= 2 poses are refined two poses per
+    wavefront (both halves of a wavefront run one ligand's control flow): with
+    k = 2 and k = 5 (a wavefront with one pose), bonds listed parents first
+    (matrices built up front) and children first (sequential torsions), and
+    ligands on both sides of 32 atoms, every refined pose and score equals the
+    FP32 oracle's bitwise; k = 1 takes the one-pose kernel and agrees too."""
+    lg = lgmod
+    import torch
+    w, pk = tiny["w"], tiny["pocket"]
+    base = tiny["ligs"].subset(np.arange(20))
+    assert (base.n_atoms <= 32).sum() >= 5 and (base.n_atoms > 32).sum() >= 5
+    pocket = device_pocket(pk)
+    rt = torch.from_numpy(tiny["r32"]).cuda()
+    at = torch.from_numpy(tiny["a32"]).cuda()
+    for label, L in (("parents first", base), ("children first", reversed_bonds(base))):
+        dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                               L.inv_bond_len, L.ref_point)
+        for k in (1, 2, 5):
+            say(f"refine pairs: {label}, k = {k}")
+            out = lg.lg_dock_batch(pocket, dl, rt, at, sweeps=w.sweeps, top_k=k, trans_samples=w.angle_samples,
+                                   trans_step=oracle.trans_step(w.angle_samples), clash_dist2=oracle.CLASH2)
+            res = lg.lg_refine(pocket, lg.docked_poses(dl, out),
+                               lg.refine_params(clash_dist2=oracle.CLASH2, poses_per_ligand=k))
+            torch.cuda.synchronize()
+            h = {key: v.cpu().numpy() for key, v in out.items()}
+            r = {key: v.cpu().numpy() for key, v in res.items()}
+            moved = 0
+            for i in range(L.n):
+                lig = L.ligand(i)
+                for q in range(k):
+                    pose = pose_of(h, L, i, q, k).astype(np.float64)
+                    sc, best, _ = oracle.refine(lig, pk, pose, h["pivot"][i, q].astype(np.float64), bits=32)
+                    np.testing.assert_array_equal(pose_of(r, L, i, q, k).astype(np.float64), best,
+                                                  err_msg=f"{label}, k={k}: ligand {i} (N={L.n_atoms[i]}) pose {q}")
+                    assert r["score"][i * k + q] == sc, (label, k, i, q)
+                    moved += not np.array_equal(best, pose)
+            assert moved > L.n * k // 2
+    pocket.free()
+
+
 def test_autotune_keeps_results(lgmod):
     """The autotuner returns a valid tuning that the handle keeps, and docking
     under it gives the same bits as under the default tuning."""
@@ -502,14 +543,16 @@ def test_bench_configuration_full_library(lgmod):
 
 def test_valu_probe_is_below_the_derived_peak(lgmod, tiny):
     """The probe's sustained rates (the roofline's measured context) are
-    positive and never above 256 CUs x 64 lanes x 2.4 GHz / 4 cycles."""
+    positive and never above the FP32 vector peak, 256 CUs x 4 SIMDs x 32 lanes
+    x 2.4 GHz; the single-operation kinds (an SGPR operand each, issued at one
+    wave64 instruction per four cycles) stay below half of it."""
     lg = lgmod
     pocket = device_pocket(tiny["pocket"])
-    derived = 256 * 4 * 16 * 2.4e9
+    peak = 256 * 4 * 32 * 2.4e9
     for kind, name in enumerate(lg.VALU_PROBE_KINDS):
-        r = lg.lg_valu_probe(pocket, kind, 20000)
+        r = lg.lg_valu_probe(pocket, kind, 20000 if kind < 6 else 2000)
         say(f"valu probe {name}: {r / 1e12:.2f} T lane-op/s")
-        assert 0.5 * derived < r < 1.02 * derived, (name, r)
+        assert 0.25 * peak < r < (0.51 if kind < 6 else 1.0) * peak, (name, r)
     with pytest.raises(lg.LgError):
         lg.lg_valu_probe(pocket, 9, 10)
     pocket.free()
