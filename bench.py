@@ -30,7 +30,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9      # CUs x SIMDs x lanes x clock: non-packed VALU issue, lane-ops/s
+# FP32 vector peak of the MI355X, 157.3 TFLOP/s, counted in lane-operations (an
+# FMA is one): 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz.  gfx950 issues a wave64
+# v_fma_f32 / v_add_f32 / v_mul_f32 with VGPR operands in two cycles (32 lanes per
+# cycle per SIMD); integer shift-adds, three-way adds, med3 and float-to-int
+# conversions take four.
+PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
+VALU_PROBE_MIX = 6   # lg_valu_probe kind: the nearest-node index sequence of a scan sample
 
 # VALU instructions per lane, per unit of work, in the inner loops of the docking
 # scans, counted in the gfx950 assembly of dock_bucket_kernel<1, 4> (four samples
@@ -558,8 +564,8 @@ def main():
                                  tune_key)
     valu_busy = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_valu.txt", "valu_busy", tune_key)
     achieved = dom_ops / (dom_ms * 1e-3)
-    # the sustained non-packed v_fma_f32 rate on this device, beside the derived peak
-    valu_meas = lg.lg_valu_probe(pocket, 0)
+    # the sustained rate of the scans' index arithmetic on this device, beside the peak
+    valu_meas = lg.lg_valu_probe(pocket, VALU_PROBE_MIX, 2000)
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(PEAK_LANE_OPS / 1e12, 3),
                     unit="TOP/s", frac=round(achieved / PEAK_LANE_OPS, 4), traffic=traffic, kernel=kernel,
                     kernel_ms=round(dom_ms, 3), ligands_in_launch=int(dom["ligands"]),
@@ -678,7 +684,8 @@ def main():
                                                 peak=round(PEAK_LANE_OPS / 1e12, 3), unit="TOP/s",
                                                 frac=round(rach / PEAK_LANE_OPS, 4), kernel="refine_kernel<s>",
                                                 algorithmic_ops=rops,
-                                                measured_valu_peak=round(lg.lg_valu_probe(pocket, 0) / 1e12, 3)))
+                                                measured_valu_peak=round(
+                                                    lg.lg_valu_probe(pocket, VALU_PROBE_MIX, 2000) / 1e12, 3)))
             if not args.no_cpu_baseline:
                 import oracle
                 hx, hy, hz = (od[c].cpu().numpy() for c in ("x", "y", "z"))

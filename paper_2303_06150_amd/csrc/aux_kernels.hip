@@ -224,8 +224,12 @@ hipError_t launch_check(const int32_t* atom_offset, const int32_t* tors_offset, 
 }
 
 // ---------------------------------------------------------------- VALU rate probe
-// Eight independent chains of one non-packed VALU operation per lane, no memory
-// traffic but one store per lane: the sustained issue rate of that operation.
+// Eight independent chains of non-packed VALU operations per lane, no memory
+// traffic but one store per lane: the sustained issue rate of one operation
+// (kinds 0-4), of two operations from different chains interleaved (5: v_fma_f32
+// and v_add_u32), and of the nearest-node index sequence of a scan sample (6:
+// v_add_f32, v_fma_f32, v_med3_f32, v_cvt_flr_i32_f32, v_lshl_add_u32,
+// v_add3_u32, v_add_f32; seven VALU operations per step of a chain).
 template <int KIND>
 __global__ __launch_bounds__(256) void valu_probe_kernel(float* out, int iters, float a, float b) {
   float x[8];
@@ -243,6 +247,18 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(float* out, int iters, 
       if (KIND == 2) y[i] = y[i] + it;                             // v_add_u32
       if (KIND == 3) x[i] = __builtin_amdgcn_fmed3f(x[i], a, b);   // v_med3_f32
       if (KIND == 4) y[i] = __mul24(y[i], 3) + it;                 // v_mad_i32_i24
+      if (KIND == 5) {
+        if (i < 4) x[i] = fmaf(x[i], a, b);
+        else y[i] = y[i] + it;
+      }
+      if (KIND == 6) {
+        const float f = __builtin_amdgcn_fmed3f(fmaf(x[i] + a, b, 0.5f), -1.0f, 90.0f);
+        int n;
+        asm volatile("v_cvt_flr_i32_f32 %0, %1" : "=v"(n) : "v"(f));
+        y[i] = (n << 2) + y[i];
+        y[i] = y[i] + n + it;
+        x[i] = x[i] + (float)(y[i] & 1);
+      }
     }
   }
   float s = 0.f;
@@ -259,6 +275,8 @@ hipError_t launch_valu_probe(int kind, int blocks, int iters, float* out, hipStr
     case 2: hipLaunchKernelGGL(valu_probe_kernel<2>, grid, block, 0, st, out, iters, 1.0001f, 0.5f); break;
     case 3: hipLaunchKernelGGL(valu_probe_kernel<3>, grid, block, 0, st, out, iters, 0.1f, 0.5f); break;
     case 4: hipLaunchKernelGGL(valu_probe_kernel<4>, grid, block, 0, st, out, iters, 0.1f, 0.5f); break;
+    case 5: hipLaunchKernelGGL(valu_probe_kernel<5>, grid, block, 0, st, out, iters, 1.0001f, 0.5f); break;
+    case 6: hipLaunchKernelGGL(valu_probe_kernel<6>, grid, block, 0, st, out, iters, 1e-7f, 1.0f); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

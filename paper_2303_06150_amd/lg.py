@@ -460,7 +460,8 @@ def refine_params(steps=50, eta_t=1e-2, eta_w=1e-3, eta_th=1e-3, clip_t=0.1, cli
                             int(poses_per_ligand))
 
 
-VALU_PROBE_KINDS = ("v_fma_f32", "v_add_f32", "v_add_u32", "v_med3_f32", "v_mad_i32_i24")
+VALU_PROBE_KINDS = ("v_fma_f32", "v_add_f32", "v_add_u32", "v_med3_f32", "v_mad_i32_i24", "v_fma_f32+v_add_u32",
+                    "scan index mix")
 
 
 def lg_valu_probe(pocket: Pocket, kind: int = 0, iters: int = 200000, stream=None) -> float:
