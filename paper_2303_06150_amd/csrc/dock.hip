@@ -24,6 +24,7 @@
 #include "lg_device.h"
 
 #include <climits>
+#include <type_traits>
 
 namespace lg {
 
@@ -41,6 +42,7 @@ struct SampleReg {
                                // (cos, sin) of the two are exact negatives
   bool quarter_turn;           // A = 64 SPL and samples j + A/4, j + A/2, j + 3A/4 are j
                                // turned by pi/2, pi, 3pi/2: (-s, c), (-c, -s), (s, -c) exactly
+  bool unit;                   // every angle sample has |cos| <= 1 and |sin| <= 1
 };
 
 
@@ -179,24 +181,33 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
                         const SampleReg<SPL>& sm, const int* tab) {
   constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
   const int lane = lane_id();
+  const float pP = p.piv[P], pQ = p.piv[Q];
+  const float cP = G.c0[P], cQ = G.c0[Q], ih = G.inv_h, fnP = G.fn[P], fnQ = G.fn[Q];
   float s0 = 0.f;
+  // With |cos|, |sin| <= 1 a rotated offset is at most |vp| + |vq| per axis
+  // (B below covers the rounding of the two products and their sum), and the
+  // node map is monotone: when both ends of every atom's range map inside
+  // [-1, n], no sample needs the clamp of the node index.
+  bool inside = true;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const int a = s * 64 + lane;
     if (a < N) {
-      float vp = p.x[P][s] - p.piv[P], vq = p.x[Q][s] - p.piv[Q];
+      float vp = p.x[P][s] - pP, vq = p.x[Q][s] - pQ;
       int ie = clamp_node(fmaf(p.x[E][s], G.inv_h, G.c0[E]), G.fn[E]);
       scr[a] = make_float4(vp, vq, __int_as_float(boff(tab + G.tab_base[E] + 1, ie)), 0.f);
       s0 += nearest(G, p.x[0][s], p.x[1][s], p.x[2][s]);
+      const float B = (fabsf(vp) + fabsf(vq)) * (1.f + 0x1p-20f);
+      inside = inside && fmaf(pP - B, ih, cP) >= -1.f && fmaf(pP + B, ih, cP) <= fnP &&
+               fmaf(pQ - B, ih, cQ) >= -1.f && fmaf(pQ + B, ih, cQ) <= fnQ;
     }
   }
+  inside = sm.unit && !wave_any(!inside);
   s0 = wave_sum(s0);
   wave_sync();
   float acc[SPL];
 #pragma unroll
   for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
-  const float pP = p.piv[P], pQ = p.piv[Q];
-  const float cP = G.c0[P], cQ = G.c0[Q], ih = G.inv_h, fnP = G.fn[P], fnQ = G.fn[Q];
   const int* tP = tab + G.tab_base[P] + 1;
   const int* tQ = tab + G.tab_base[Q] + 1;
   const char* gk = G.gk;
@@ -256,7 +267,32 @@ __device__ int rot_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, i
       out[q + 3 * Q4] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
     }
   };
-  if (SPL % 4 == 0 && sm.quarter_turn)
+  // the same, every node index known to lie in range (no clamp)
+  auto gather_quarter_turn_inside = [&](int t, float (&out)[SPL]) {
+    const float4 d = scr[t];
+    const int part = __float_as_int(d.z);
+    constexpr int Q4 = SPL / 4;
+#pragma unroll
+    for (int q = 0; q < Q4; ++q) {
+      const float np = fmaf(sm.c[q], d.x, -(sm.s[q] * d.y));
+      const float nq = fmaf(sm.s[q], d.x, sm.c[q] * d.y);
+      int ip = floor_node(fmaf(pP + np, ih, cP));
+      int iq = floor_node(fmaf(pQ + nq, ih, cQ));
+      out[q] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+      ip = floor_node(fmaf(pP - nq, ih, cP));
+      iq = floor_node(fmaf(pQ + np, ih, cQ));
+      out[q + Q4] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+      ip = floor_node(fmaf(pP - np, ih, cP));
+      iq = floor_node(fmaf(pQ - nq, ih, cQ));
+      out[q + 2 * Q4] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+      ip = floor_node(fmaf(pP + nq, ih, cP));
+      iq = floor_node(fmaf(pQ - np, ih, cQ));
+      out[q + 3 * Q4] = grid_at(gk, part + boff(tP, ip) + boff(tQ, iq));
+    }
+  };
+  if (SPL % 4 == 0 && sm.quarter_turn && inside)
+    pipelined_sum<SPL>(N, gather_quarter_turn_inside, acc);
+  else if (SPL % 4 == 0 && sm.quarter_turn)
     pipelined_sum<SPL>(N, gather_quarter_turn, acc);
   else if (SPL % 2 == 0 && sm.half_turn)
     pipelined_sum<SPL>(N, gather_half_turn, acc);
@@ -298,6 +334,7 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
   const float da = D.delta * (float)mlo, db = D.delta * (float)mhi;
   const float dmin = fminf(da, db), dmax = fmaxf(da, db);
   int span = 0;
+  bool inside = true;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const int a = s * 64 + lane;
@@ -308,10 +345,12 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
       const int lo = clamp_node(fmaf(p.x[E][s] + dmin, ih, cE), fnE);
       const int hi = clamp_node(fmaf(p.x[E][s] + dmax, ih, cE), fnE);
       span = max(span, hi - lo + 1);
+      inside = inside && lo >= 0 && hi < G.n[E];   // every sample's f in [0, n): no clamp needed
       scr[a] = make_float4(p.x[E][s], __int_as_float(part), __int_as_float(lo), 0.f);
     }
   }
   span = wave_reduce_i32(span, OpMax());
+  inside = !wave_any(!inside);
   wave_sync();
   float acc[SPL];
 #pragma unroll
@@ -346,29 +385,39 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
       return v;
     };
     const int groups = (N + per - 1) / per;
-    float next = stage_load(0);
-    for (int g = 0; g < groups; ++g) {
-      float* buf = stage + (g & 1) * 64;    // two buffers: this group's stage is written while
-      buf[lane] = next;                     // the previous group's reads are retired
-      wave_sync();
-      if (g + 1 < groups) next = stage_load(g + 1);
-      const int t0 = g * per, t1 = min(N, t0 + per);
-      for (int t = t0; t < t1; ++t) {
-        const float4 d = scr[t];
-        // LDS byte address of the atom's run, shifted so that node ie (in [lo, lo +
-        // span)) is at run + 4 ie
-        uint32_t run = lds_addr(buf) + 4u * (uint32_t)((t - t0) * span - __float_as_int(d.z));
-        asm volatile("" : "+v"(run));   // one base per atom: each sample then adds 4 ie in one shift-add
-        int ie[SPL];
-        float v[SPL];
+    auto staged = [&](auto clamp_tag) {
+      constexpr bool CLAMP = decltype(clamp_tag)::value;
+      float next = stage_load(0);
+      for (int g = 0; g < groups; ++g) {
+        float* buf = stage + (g & 1) * 64;    // two buffers: this group's stage is written while
+        buf[lane] = next;                     // the previous group's reads are retired
+        wave_sync();
+        if (g + 1 < groups) next = stage_load(g + 1);
+        const int t0 = g * per, t1 = min(N, t0 + per);
+        for (int t = t0; t < t1; ++t) {
+          const float4 d = scr[t];
+          // LDS byte address of the atom's run, shifted so that node ie (in [lo, lo +
+          // span)) is at run + 4 ie
+          uint32_t run = lds_addr(buf) + 4u * (uint32_t)((t - t0) * span - __float_as_int(d.z));
+          asm volatile("" : "+v"(run));   // one base per atom: each sample then adds 4 ie in one shift-add
+          int ie[SPL];
+          float v[SPL];
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) ie[q] = clamp_node(fmaf(d.x + sm.d[q], ih, cE), fnE);
+          for (int q = 0; q < SPL; ++q) {
+            const float f = fmaf(d.x + sm.d[q], ih, cE);
+            ie[q] = CLAMP ? clamp_node(f, fnE) : floor_node(f);
+          }
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) v[q] = lds_load(run + 4u * (uint32_t)ie[q]);
+          for (int q = 0; q < SPL; ++q) v[q] = lds_load(run + 4u * (uint32_t)ie[q]);
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) acc[q] += v[q];
+          for (int q = 0; q < SPL; ++q) acc[q] += v[q];
+        }
       }
-    }
+    };
+    if (inside)
+      staged(std::false_type{});
+    else
+      staged(std::true_type{});
   }
   const int j = wave_argmax(acc, sm.valid_t);
   apply_trans<NSLOT, E>(D, p, j);
@@ -561,6 +610,12 @@ __device__ void load_samples(const DockDev& D, SampleReg<SPL>& sm) {
     } else {
       sm.d[q] = 0.f;
     }
+  }
+  {
+    bool u = true;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) u = u && fabsf(sm.c[q]) <= 1.f && fabsf(sm.s[q]) <= 1.f;
+    sm.unit = !wave_any(!u);
   }
   if (SPL % 2 == 0 && D.A == 64 * SPL) {
     bool pair = true;

@@ -190,6 +190,13 @@ __device__ __forceinline__ int orderable(float f) {
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 
+// Floor of f for a node map value already known to lie in [-1, n].
+__device__ __forceinline__ int floor_node(float f) {
+  int i;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(f));
+  return i;
+}
+
 // Node index on the padded grid for coordinate offset f (already scaled):
 // floor of f clamped to [-1, n] -- -1 and n land on the out_value border.
 __device__ __forceinline__ int clamp_node(float f, float fn) {
