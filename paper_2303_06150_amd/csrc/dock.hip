@@ -321,8 +321,10 @@ __device__ __forceinline__ float lds_load(uint32_t addr) {
 // per gather instruction, into an LDS stage -- and every sample then takes its
 // value from the stage: the same value, node and sum order as a direct gather
 // per sample, with a fraction of the gather instructions.  Runs longer than a
-// wavefront (very wide translation ranges) fall back to direct gathers.
-template <int NSLOT, int SPL, int E>
+// wavefront (very wide translation ranges) fall back to direct gathers, and so
+// does STAGE = false (the plain launch, where a lone wavefront per SIMD would
+// wait on every group's nodes).
+template <int NSLOT, int SPL, int E, bool STAGE>
 __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p, int N, float4* scr, float* stage,
                           const SampleReg<SPL>& sm, const int* tab) {
   constexpr int P = (E + 1) % 3, Q = (E + 2) % 3;
@@ -357,7 +359,7 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
   for (int q = 0; q < SPL; ++q) acc[q] = 0.f;
   const int* tE = tab + G.tab_base[E] + 1;
   const char* gk = G.gk;
-  if (span > 64) {
+  if (!STAGE || span > 64) {
     auto gather = [&](int t, float (&out)[SPL]) {
       const float4 d = scr[t];
       const int part = __float_as_int(d.y);
@@ -425,6 +427,12 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
   return j;
 }
 
+// Square root for the pair prune's radii: the hardware's one-ulp root.  The
+// prune only has to keep every pair that can clash, and its 0.05 A margin is
+// orders of magnitude above an ulp of a radius (the exact clash test itself
+// uses no root).
+__device__ __forceinline__ float prune_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---- greedy torsion scan of bond k with the clash check ----------------------
 // Admissibility of every sample is decided in the scoring pass.  A moving atom
 // sweeps a circle about the bond axis; a (moving, static) pair whose circle never
@@ -459,7 +467,7 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
     st[s] = in && !inf && at != a;
     const float vx = p.x[0][s] - xa, vy = p.x[1][s] - ya, vz = p.x[2][s] - za;
     hs[s] = vx * ux + vy * uy + vz * uz;
-    rs[s] = sqrtf(fmaxf(vx * vx + vy * vy + vz * vz - hs[s] * hs[s], 0.f));
+    rs[s] = prune_sqrt(fmaxf(vx * vx + vy * vy + vz * vz - hs[s] * hs[s], 0.f));
     const uint64_t bal = __ballot(mv[s]);
     const int pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
     if (mv[s]) {
@@ -476,7 +484,7 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
   for (int t = 0; t < m; ++t) {
     const float4 v = scr[t];
     const float ht = v.x * ux + v.y * uy + v.z * uz;
-    const float rt = sqrtf(fmaxf(v.x * v.x + v.y * v.y + v.z * v.z - ht * ht, 0.f));
+    const float rt = prune_sqrt(fmaxf(v.x * v.x + v.y * v.y + v.z * v.z - ht * ht, 0.f));
     const int first = npairs;
 #pragma unroll
     for (int s = 0; s < NSLOT; ++s) {
@@ -697,7 +705,7 @@ __device__ __forceinline__ uint16_t* move_record(const DockDev& D, int lig, int 
 }
 
 // One restart: placement, S sweeps, final trilinear score, outputs.
-template <int NSLOT, int SPL>
+template <int NSLOT, int SPL, bool STAGE = true>
 __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& D, const SampleReg<SPL>& sm,
                              const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand, const int* tab) {
   const int lane = lane_id();
@@ -712,9 +720,9 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
     int jr1 = rot_scan<NSLOT, SPL, 1>(G, D, p, N, scr, sm, tab);
     int jr2 = rot_scan<NSLOT, SPL, 2>(G, D, p, N, scr, sm, tab);
     float* stage = reinterpret_cast<float*>(cand);
-    int jt0 = trans_scan<NSLOT, SPL, 0>(G, D, p, N, scr, stage, sm, tab);
-    int jt1 = trans_scan<NSLOT, SPL, 1>(G, D, p, N, scr, stage, sm, tab);
-    int jt2 = trans_scan<NSLOT, SPL, 2>(G, D, p, N, scr, stage, sm, tab);
+    int jt0 = trans_scan<NSLOT, SPL, 0, STAGE>(G, D, p, N, scr, stage, sm, tab);
+    int jt1 = trans_scan<NSLOT, SPL, 1, STAGE>(G, D, p, N, scr, stage, sm, tab);
+    int jt2 = trans_scan<NSLOT, SPL, 2, STAGE>(G, D, p, N, scr, stage, sm, tab);
     int16_t* trow = tr ? tr + (size_t)sw * D.trace_w : nullptr;
     uint16_t* mrow = mrec + (size_t)sw * (6 + L.K);
     if (lane == 0) {
@@ -797,7 +805,9 @@ __global__ __launch_bounds__(256) void dock_plain_kernel(GridDev G, LigDev Lg, D
   load_samples(D, sm);
   LigReg<NSLOT> L;
   load_ligand(Lg, lig, L);
-  dock_restart(G, Lg, D, sm, L, lig, r, scr, cand, tab);
+  // one wavefront per restart: the staged translation scan's read-then-use of
+  // each group's nodes would expose their latency, so the gathers stay direct
+  dock_restart<NSLOT, SPL, false>(G, Lg, D, sm, L, lig, r, scr, cand, tab);
 }
 
 // Bucketed method: persistent; wavefronts pull (ligand, restart chunk) items of
