@@ -144,6 +144,14 @@ def bucket_of(n_atoms, n_tors, tuning):
     return ca * nr + cr
 
 
+# Tuning of the bucketed path on the mixed workload: size classes of at most 64,
+# 128, 192 and 256 atoms, one bond class, two restarts per work item, two
+# wavefronts per block for the one-slot kernel and four for the others.  The
+# library's search (--autotune-ligands) lands within run-to-run noise of it.
+DEFAULT_TUNING = {"atom_bounds": [64, 128, 192, 256], "rot_bounds": [32], "restart_chunk": 2, "grid_scale": 1,
+                  "waves_per_block": [2, 4, 4, 4], "lazy_clash": 0}
+
+
 def kernel_tag(stat):
     return f"dock_bucket_{stat['slots']}_{stat['samples_per_lane']}"
 
@@ -391,13 +399,14 @@ def main():
     ap.add_argument("--ablation-ligands", type=int, default=20000)
     ap.add_argument("--stream-chunk", type=int, default=25000,
                     help="side run: the library docked from host memory in chunks of this many ligands (0: skip)")
-    ap.add_argument("--autotune-ligands", type=int, default=16000,
-                    help="tune the bucketed path on this many ligands before timing (0: default tuning); a "
-                         "small sample favours fewer buckets, whose second launch it cannot fill")
-    ap.add_argument("--tuning", default=None,
+    ap.add_argument("--autotune-ligands", type=int, default=0,
+                    help="tune the bucketed path on this many ligands before timing instead of using "
+                         "--tuning (0: no search); a small sample favours fewer buckets, whose second launch "
+                         "it cannot fill")
+    ap.add_argument("--tuning", default=json.dumps(DEFAULT_TUNING),
                     help="JSON object of tuning fields (atom_bounds, rot_bounds, restart_chunk, grid_scale, "
-                         "waves_per_block, lazy_clash) to use instead of autotuning, e.g. to take counters on "
-                         "the tuning an earlier run chose")
+                         "waves_per_block, lazy_clash); the default is the best of a sweep on the mixed "
+                         "workload, the tuning the committed counter summaries were taken on")
     ap.add_argument("--refine-ligands", type=int, default=20000,
                     help="side run: refine the top --refine-poses poses of this many ligands (0: skip)")
     ap.add_argument("--refine-poses", type=int, default=64)
@@ -463,7 +472,7 @@ def main():
 
     # ---- autotuning on a prefix of the library (reported, not timed)
     tune = None
-    if args.tuning:
+    if args.tuning and args.autotune_ligands <= 0:
         spec = json.loads(args.tuning)
         t = pocket.get_tuning()
         t.n_atom_clusters = len(spec["atom_bounds"])

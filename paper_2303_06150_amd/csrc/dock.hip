@@ -433,6 +433,16 @@ __device__ int trans_scan(const GridDev& G, const DockDev& D, PoseReg<NSLOT>& p,
 // uses no root).
 __device__ __forceinline__ float prune_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Minimum of two floats as one v_min_f32: fminf's quieting of signalling NaNs
+// costs two more instructions per call on a loop-carried value.  A NaN operand
+// yields the other one, so a NaN distance never counts as a clash, as with the
+// comparison d^2 < clash^2.
+__device__ __forceinline__ float vmin(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // ---- greedy torsion scan of bond k with the clash check ----------------------
 // Admissibility of every sample is decided in the scoring pass.  A moving atom
 // sweeps a circle about the bond axis; a (moving, static) pair whose circle never
@@ -532,16 +542,25 @@ __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, P
           out[q] = grid_at(gk, boff(tX, ix) + boff(tY, iy) + boff(tZ, iz));
         }
         if (!overflow) {
-          const int seg = __float_as_int(v.w);
+          // the segment is the same on every lane: a scalar loop; the least d^2
+          // over the atom's pairs decides its clash bits (min is exact)
+          const int seg = __builtin_amdgcn_readfirstlane(__float_as_int(v.w));
           const int p0 = seg & 0xFFFF, p1 = p0 + (seg >> 16);
-          for (int pi = p0; pi < p1; ++pi) {
-            const float4 c = pairs[pi];
+          if (p1 > p0) {
+            float dmin[QG];
 #pragma unroll
-            for (int q = 0; q < QG; ++q) {
-              float dx = X[q] - c.x, dy = Y[q] - c.y, dz = Z[q] - c.z;
-              float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-              if (d2 < clash2) clash |= 1u << (g + q);
+            for (int q = 0; q < QG; ++q) dmin[q] = __builtin_inff();
+            for (int pi = p0; pi < p1; ++pi) {
+              const float4 c = pairs[pi];
+#pragma unroll
+              for (int q = 0; q < QG; ++q) {
+                float dx = X[q] - c.x, dy = Y[q] - c.y, dz = Z[q] - c.z;
+                dmin[q] = vmin(dmin[q], fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+              }
             }
+#pragma unroll
+            for (int q = 0; q < QG; ++q)
+              if (dmin[q] < clash2) clash |= 1u << (g + q);
           }
         }
       };
