@@ -469,7 +469,7 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
         b.samples_per_lane = spl;
         b.waves_per_block = wpb;
         b.vgprs = attr.numRegs;
-        b.lds_bytes = (int32_t)((size_t)((p->grid.tab_len + 3) & ~3) * 4 + (size_t)wpb * 3 * 64 * nslot * 16);
+        b.lds_bytes = (int32_t)((size_t)((p->grid.tab_len + 3) & ~3) * 4 + (size_t)wpb * lg::dock_wave_float4(nslot) * 16);
         b.blocks_per_cu = bpc;
         b.blocks = bpc * p->cus * tu.grid_scale;
         b.ligands = -1;

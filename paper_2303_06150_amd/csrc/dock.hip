@@ -454,10 +454,13 @@ __device__ __forceinline__ float vmin(float a, float b) {
 // against every pair and dropped while it clashes (same result, slower).
 template <int NSLOT, int SPL>
 __device__ int tors_scan(const GridDev& G, const LigDev& Lg, const DockDev& D, PoseReg<NSLOT>& p, int N,
-                         int toff, int k, const uint32_t (&mk)[NSLOT], float4* scr, float4* pairs,
+                         int toff, int k, const uint32_t* mkl, float4* scr, float4* pairs,
                          const SampleReg<SPL>& sm, const int* tab) {
   constexpr int PAIR_CAP = 128 * NSLOT;
   const int lane = lane_id();
+  uint32_t mk[NSLOT];   // fragment masks of this lane's atoms, kept in LDS between scans
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) mk[s] = mkl[s * 64 + lane];
   const BondAxis A = bond_axis(Lg, p, toff, k);
   const int a = A.a, b = A.b;
   const float xa = A.xa, ya = A.ya, za = A.za, ux = A.ux, uy = A.uy, uz = A.uz;
@@ -686,6 +689,17 @@ __device__ void load_ligand(const LigDev& Lg, int lig, LigReg<NSLOT>& L) {
   for (int c = 0; c < 3; ++c) L.P0[c] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(Lg.ref[3 * lig + c])));
 }
 
+// The fragment masks of the ligand's atoms into the wavefront's LDS: read by
+// every torsion scan, they would otherwise be held in registers through the
+// restart loop (and spilled to scratch at the register budget of the persistent
+// instances, a store per work item).  Each lane reads back only its own words.
+template <int NSLOT>
+__device__ __forceinline__ void store_masks(const LigReg<NSLOT>& L, uint32_t* mkl) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) mkl[s * 64 + lane] = L.mk[s];
+}
+
 // Restart placement: x = M_r (x0 - P0) + (c + t_r), pivot c + t_r.
 template <int NSLOT>
 __device__ __forceinline__ void place_pose(const LigDev& Lg, const DockDev& D, const LigReg<NSLOT>& L, int r,
@@ -726,7 +740,8 @@ __device__ __forceinline__ uint16_t* move_record(const DockDev& D, int lig, int 
 // One restart: placement, S sweeps, final trilinear score, outputs.
 template <int NSLOT, int SPL, bool STAGE = true>
 __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& D, const SampleReg<SPL>& sm,
-                             const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand, const int* tab) {
+                             const LigReg<NSLOT>& L, int lig, int r, float4* scr, float4* cand,
+                             const uint32_t* mkl, const int* tab) {
   const int lane = lane_id();
   const int N = L.N;
   PoseReg<NSLOT> p;
@@ -753,7 +768,7 @@ __device__ void dock_restart(const GridDev& G, const LigDev& Lg, const DockDev& 
       trow[3] = (int16_t)jt0; trow[4] = (int16_t)jt1; trow[5] = (int16_t)jt2;
     }
     for (int k = 0; k < L.K; ++k) {
-      int jk = tors_scan<NSLOT, SPL>(G, Lg, D, p, N, L.toff, k, L.mk, scr, cand, sm, tab);
+      int jk = tors_scan<NSLOT, SPL>(G, Lg, D, p, N, L.toff, k, mkl, scr, cand, sm, tab);
       if (lane == 0) mrow[6 + k] = (uint16_t)jk;
       if (trow && lane == 0) trow[6 + k] = (int16_t)jk;
     }
@@ -806,7 +821,7 @@ __device__ void replay_restart(const LigDev& Lg, const DockDev& D, const LigReg<
 
 // Plain method: one launch per ligand; wavefront w of the grid docks restart w.
 // LDS of a block: the brick offset tables, then per wavefront the scan data of
-// 64*NSLOT atoms and a list of 128*NSLOT risky torsion pairs.
+// 64*NSLOT atoms, a list of 128*NSLOT risky torsion pairs and the fragment masks.
 __device__ __forceinline__ int tab_words(const GridDev& G) { return (G.tab_len + 3) & ~3; }
 
 template <int NSLOT, int SPL>
@@ -816,17 +831,19 @@ __global__ __launch_bounds__(256) void dock_plain_kernel(GridDev G, LigDev Lg, D
   fill_brick_tables(G, tab);
   __syncthreads();
   const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * (3 * 64 * NSLOT);
+  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * dock_wave_float4(NSLOT);
   float4* cand = scr + 64 * NSLOT;
+  uint32_t* mkl = reinterpret_cast<uint32_t*>(scr + 3 * 64 * NSLOT);
   const int r = blockIdx.x * nwaves + wave;
   if (r >= D.R) return;
   SampleReg<SPL> sm;
   load_samples(D, sm);
   LigReg<NSLOT> L;
   load_ligand(Lg, lig, L);
+  store_masks(L, mkl);
   // one wavefront per restart: the staged translation scan's read-then-use of
   // each group's nodes would expose their latency, so the gathers stay direct
-  dock_restart<NSLOT, SPL, false>(G, Lg, D, sm, L, lig, r, scr, cand, tab);
+  dock_restart<NSLOT, SPL, false>(G, Lg, D, sm, L, lig, r, scr, cand, mkl, tab);
 }
 
 // Bucketed method: persistent; wavefronts pull (ligand, restart chunk) items of
@@ -844,8 +861,9 @@ void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
   fill_brick_tables(G, tab);
   __syncthreads();
   const int wave = threadIdx.x >> 6;
-  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * (3 * 64 * NSLOT);
+  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * dock_wave_float4(NSLOT);
   float4* cand = scr + 64 * NSLOT;
+  uint32_t* mkl = reinterpret_cast<uint32_t*>(scr + 3 * 64 * NSLOT);
   const int lane = lane_id();
   const int b0 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket]);
   const int b1 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket + 1]);
@@ -865,6 +883,7 @@ void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
     const int lig = __builtin_amdgcn_readfirstlane(Q.perm[b0 + li]);
     if (lig != cur_lig) {
       load_ligand(Lg, lig, L);
+      store_masks(L, mkl);
       cur_lig = lig;
     }
     const int r0 = ch * Q.chunk, r1 = min(D.R, r0 + Q.chunk);
@@ -874,7 +893,7 @@ void dock_bucket_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q) {
       for (int r = r0 + lane; r < r1; r += 64) D.final_scores[(size_t)lig * D.R + r] = __builtin_nanf("");
       continue;
     }
-    for (int r = r0; r < r1; ++r) dock_restart(G, Lg, D, sm, L, lig, r, scr, cand, tab);
+    for (int r = r0; r < r1; ++r) dock_restart(G, Lg, D, sm, L, lig, r, scr, cand, mkl, tab);
   }
 }
 
@@ -890,8 +909,9 @@ void dock_sites_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q, SitesDev Sd)
   fill_brick_tables(G, tab);
   __syncthreads();
   const int wave = threadIdx.x >> 6;
-  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * (3 * 64 * NSLOT);
+  float4* scr = lds + tab_words(G) / 4 + (size_t)wave * dock_wave_float4(NSLOT);
   float4* cand = scr + 64 * NSLOT;
+  uint32_t* mkl = reinterpret_cast<uint32_t*>(scr + 3 * 64 * NSLOT);
   const int lane = lane_id();
   const int b0 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket]);
   const int b1 = __builtin_amdgcn_readfirstlane(Q.bucket_start[Q.bucket + 1]);
@@ -924,6 +944,7 @@ void dock_sites_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q, SitesDev Sd)
     const int lig = __builtin_amdgcn_readfirstlane(Q.perm[b0 + li]);
     if (lig != cur_lig) {
       load_ligand(Lg, lig, L);
+      store_masks(L, mkl);
       cur_lig = lig;
     }
     // the site's fields as uniform words: a plain load of Sd.grids would be
@@ -954,7 +975,7 @@ void dock_sites_kernel(GridDev G, LigDev Lg, DockDev D, QueueDev Q, SitesDev Sd)
       for (int r = r0 + lane; r < r1; r += 64) Ds.final_scores[(size_t)lig * D.R + r] = __builtin_nanf("");
       continue;
     }
-    for (int r = r0; r < r1; ++r) dock_restart(Gs, Lg, Ds, sm, L, lig, r, scr, cand, tab);
+    for (int r = r0; r < r1; ++r) dock_restart(Gs, Lg, Ds, sm, L, lig, r, scr, cand, mkl, tab);
   }
 }
 
@@ -1008,9 +1029,10 @@ __global__ __launch_bounds__(256) void topk_kernel(LigDev Lg, DockDev D, int n, 
 }
 
 // ---------------------------------------------------------------- dispatch
-// LDS per block: per wavefront, scan data and torsion candidates of 64*NSLOT atoms.
+// LDS per block: the brick offset tables, then per wavefront the scan data,
+// torsion candidates and fragment masks of 64*NSLOT atoms.
 static size_t lds_bytes(int nslot, int wpb, int tab_len) {
-  return (size_t)((tab_len + 3) & ~3) * sizeof(int) + (size_t)wpb * 3 * 64 * nslot * sizeof(float4);
+  return (size_t)((tab_len + 3) & ~3) * sizeof(int) + (size_t)wpb * dock_wave_float4(nslot) * sizeof(float4);
 }
 
 #define LG_DISPATCH(nslot, spl, CALL)                                          \

@@ -102,6 +102,11 @@ struct SitesDev {
 
 // Persistent work source of one bucket: items are (ligand of the bucket,
 // chunk of `chunk` restarts), pulled from `cursor` by whole wavefronts.
+// LDS of a docking wavefront, in float4: scan data of 64*nslot atoms, two
+// regions of 64*nslot float4 (risky torsion pairs or staged grid values), the
+// ligand's fragment masks (one 32-bit word per atom).
+constexpr int dock_wave_float4(int nslot) { return 3 * 64 * nslot + 16 * nslot; }
+
 struct QueueDev {
   const int32_t* perm;          // ligand ids grouped by bucket
   const int32_t* bucket_start;  // [B+1]
