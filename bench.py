@@ -40,15 +40,18 @@ VALU_PROBE_MIX = 6   # lg_valu_probe kind: the nearest-node index sequence of a 
 
 # VALU instructions per lane, per unit of work, in the inner loops of the docking
 # scans, counted in the gfx950 assembly of dock_bucket_kernel<1, 4> (four samples
-# per lane, loop control included): a loop pass of the rotation scan handles two
-# atoms x four samples in 107 (the lane's four quarter-turn samples share one 2-D
-# rotation), of the translation scan two atoms x four samples in 58, of the
-# torsion scan one moving atom x two samples in 58 plus 6 per two atoms; each
-# torsion sample's rotation matrix takes 13.  Placement and the final trilinear
-# score are counted from the op script (15 and 45 per atom and restart).
-ISA_ROT = 107 / 8        # per (rotation sample, atom)
-ISA_TRANS = 58 / 8       # per (translation sample, atom)
-ISA_TORS = 29 + 6 / 4    # per (torsion sample, moving atom)
+# per lane, loop control included), for the variants a scan takes when every
+# sample's node is inside the grid (the usual case): a loop pass of the rotation
+# scan handles two atoms x four samples in 91 (the lane's four quarter-turn
+# samples share one 2-D rotation), of the staged translation scan one atom x four
+# samples in 25 (node values read from LDS; the group gathers that stage them are
+# not counted), of the torsion scan two moving atoms x two samples in 132 (the
+# per-atom set-up of the clash-pair loop included, the pair tests themselves
+# not); each torsion sample's rotation matrix takes 13.  Placement and the final
+# trilinear score are counted from the op script (15 and 45 per atom and restart).
+ISA_ROT = 91 / 8         # per (rotation sample, atom)
+ISA_TRANS = 25 / 4       # per (translation sample, atom)
+ISA_TORS = 132 / 4       # per (torsion sample, moving atom)
 ISA_TMAT = 13            # per torsion sample
 OPS_PLACE = 15           # per atom per restart: placement
 OPS_TRI = 45             # per atom per restart: trilinear final score
