@@ -575,6 +575,8 @@ def main():
     traffic = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_traffic.txt", "hbm_bytes_per_dispatch",
                                  tune_key)
     valu_busy = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_valu.txt", "valu_busy", tune_key)
+    valu_issue = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_valu.txt", "valu_issue_per_simd_cycle",
+                                    tune_key)
     achieved = dom_ops / (dom_ms * 1e-3)
     # the sustained rate of the scans' index arithmetic on this device, beside the peak
     valu_meas = lg.lg_valu_probe(pocket, VALU_PROBE_MIX, 2000)
@@ -585,6 +587,9 @@ def main():
                     ops_basis="VALU lane-ops of the scans' inner loops, every sample of every scan (gfx950 "
                               "assembly count per unit; pair tests and per-scan work not counted)",
                     valu_busy=valu_busy,
+                    # every VALU instruction the counters saw, against gfx950's issue limit of one
+                    # wave64 VALU instruction per SIMD per two cycles (the 78.6 T lane-op peak)
+                    valu_issue_frac=round(2.0 * valu_issue, 4) if valu_issue is not None else None,
                     gather_bw=round(4.0 * dom_looks / (dom_ms * 1e-3) / 1e9, 1), gather_unit="GB/s",
                     measured_valu_peak=round(valu_meas / 1e12, 3),
                     plain_method=dict(ops_per_launch=dom_plain,
