@@ -577,6 +577,7 @@ def main():
     valu_busy = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_valu.txt", "valu_busy", tune_key)
     valu_issue = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_valu.txt", "valu_issue_per_simd_cycle",
                                     tune_key)
+    l2_hit = read_profile_value(f"{kernel_tag(dom)}_{args.workload}_valu.txt", "l2_hit", tune_key)
     achieved = dom_ops / (dom_ms * 1e-3)
     # the sustained rate of the scans' index arithmetic on this device, beside the peak
     valu_meas = lg.lg_valu_probe(pocket, VALU_PROBE_MIX, 2000)
@@ -590,6 +591,7 @@ def main():
                     # every VALU instruction the counters saw, against gfx950's issue limit of one
                     # wave64 VALU instruction per SIMD per two cycles (the 78.6 T lane-op peak)
                     valu_issue_frac=round(2.0 * valu_issue, 4) if valu_issue is not None else None,
+                    l2_hit=l2_hit,   # TCC hits / (hits + misses) of the launch: the grid stays L2-resident
                     gather_bw=round(4.0 * dom_looks / (dom_ms * 1e-3) / 1e9, 1), gather_unit="GB/s",
                     measured_valu_peak=round(valu_meas / 1e12, 3),
                     plain_method=dict(ops_per_launch=dom_plain,

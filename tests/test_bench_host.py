@@ -30,7 +30,7 @@ def parse(path):
 @pytest.mark.parametrize("name,fields", [
     ("dock_bucket_1_4_mixed_traffic.txt", ("fetch_bytes_per_dispatch", "write_bytes_per_dispatch",
                                            "hbm_bytes_per_dispatch")),
-    ("dock_bucket_1_4_mixed_valu.txt", ("valu_busy", "valu_issue_per_simd_cycle", "td_busy", "ta_busy")),
+    ("dock_bucket_1_4_mixed_valu.txt", ("valu_busy", "valu_issue_per_simd_cycle", "td_busy", "ta_busy", "l2_hit")),
 ])
 def test_committed_counter_summaries(name, fields, tmp_path, monkeypatch):
     """Each summary names its commands, the kernel source and tuning it was taken
