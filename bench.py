@@ -165,9 +165,13 @@ def tuning_key(t):
             f"chunk {t.restart_chunk} scale {t.grid_scale} waves {list(t.waves_per_block)} lazy {t.lazy_clash}")
 
 
-def read_profile_value(name, field, tune_key):
+DOCK_SOURCES = ("dock.hip", "lg_internal.h", "lg_device.h")
+REFINE_SOURCES = ("refine.hip", "lg_internal.h", "lg_device.h")
+
+
+def read_profile_value(name, field, tune_key, sources=DOCK_SOURCES):
     """A figure of a committed rocprofv3 counter summary under profiles/, if it was
-    taken on the current kernel source and the same tuning (else None)."""
+    taken on the current source of its kernels and the same tuning (else None)."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -176,7 +180,7 @@ def read_profile_value(name, field, tune_key):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != source_hash() or kv.get("tuning") != tune_key:
+    if kv.get("source_sha256") != source_hash(sources) or kv.get("tuning") != tune_key:
         return None
     try:
         return float(kv[field])
@@ -184,9 +188,9 @@ def read_profile_value(name, field, tune_key):
         return None
 
 
-def source_hash():
+def source_hash(sources=DOCK_SOURCES):
     h = hashlib.sha256()
-    for f in ("dock.hip", "lg_internal.h", "lg_device.h"):
+    for f in sources:
         h.update(open(os.path.join(ROOT, "paper_2303_06150_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -705,6 +709,11 @@ def main():
                                                 algorithmic_ops=rops,
                                                 measured_valu_peak=round(
                                                     lg.lg_valu_probe(pocket, VALU_PROBE_MIX, 2000) / 1e12, 3)))
+            # the refinement kernels' VALU issue from the committed counter summary
+            # (time-weighted over the size classes), against the dual-rate limit
+            rvi = read_profile_value("refine_mixed20k_counters.md", "valu_issue_per_simd_cycle", "refine",
+                                     REFINE_SOURCES)
+            side["refine"]["roofline"]["valu_issue_frac"] = round(2.0 * rvi, 4) if rvi is not None else None
             if not args.no_cpu_baseline:
                 import oracle
                 hx, hy, hz = (od[c].cpu().numpy() for c in ("x", "y", "z"))

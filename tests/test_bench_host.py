@@ -31,6 +31,7 @@ def parse(path):
     ("dock_bucket_1_4_mixed_traffic.txt", ("fetch_bytes_per_dispatch", "write_bytes_per_dispatch",
                                            "hbm_bytes_per_dispatch")),
     ("dock_bucket_1_4_mixed_valu.txt", ("valu_busy", "valu_issue_per_simd_cycle", "td_busy", "ta_busy", "l2_hit")),
+    ("refine_mixed20k_counters.md", ("valu_issue_per_simd_cycle",)),
 ])
 def test_committed_counter_summaries(name, fields, tmp_path, monkeypatch):
     """Each summary names its commands, the kernel source and tuning it was taken
@@ -45,11 +46,11 @@ def test_committed_counter_summaries(name, fields, tmp_path, monkeypatch):
     assert float(kv.get("hbm_bytes_per_dispatch", 1)) == pytest.approx(
         float(kv.get("fetch_bytes_per_dispatch", 0.5)) + float(kv.get("write_bytes_per_dispatch", 0.5)), rel=1e-5)
     # read through bench's own reader in a copy of the tree whose source hash matches
-    monkeypatch.setattr(bench, "source_hash", lambda: kv["source_sha256"])
+    monkeypatch.setattr(bench, "source_hash", lambda *a: kv["source_sha256"])
     key = kv["tuning"]
     assert bench.read_profile_value(name, fields[0], key) == pytest.approx(float(kv[fields[0]]))
     assert bench.read_profile_value(name, fields[0], key + " other") is None
-    monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
+    monkeypatch.setattr(bench, "source_hash", lambda *a: "0" * 16)
     assert bench.read_profile_value(name, fields[0], key) is None
     assert bench.read_profile_value("no_such_summary.txt", fields[0], key) is None
 
