@@ -430,7 +430,7 @@ def main():
                     help="also run a 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build docks on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark docks on one GPU; --gpus {args.gpus} is not supported "
               "(ligands shard across GPUs with no exchange but the final ranking).", file=sys.stderr)
         sys.exit(2)
 

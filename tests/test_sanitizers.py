@@ -2,7 +2,7 @@
 sanitizers (no GPU): the library's argument checks (plain C++, the same source
 the library links) against random and malformed batches, and the CPU oracle and
 the input generators on ligands of 1 to 64 atoms.  Any out-of-bounds access,
-use after free, leak or undefined behaviour aborts the driver."""
+use after free, leak or undefined behaviour aborts the test program."""
 import os
 import shutil
 import subprocess
