@@ -472,8 +472,8 @@ def test_degenerate_cases(lgmod, tiny):
 
 
 def test_bench_configuration_full_library(lgmod):
-    """The benchmark's own configuration: the whole 100k mixed library, buckets
-    chosen by the autotuner, docked through the graph replay.  Sampled restarts
+    """The benchmark's own configuration: the whole 100k mixed library in
+    bench.py's tuning, docked through the graph replay.  Sampled restarts
     and one ligand's full top-10 against the oracle; at full size, properties
     that hold for every ligand: top-k sorted (equal scores: lower restart),
     kept scores equal to those restarts' final scores, every kept pose keeps
@@ -490,11 +490,20 @@ def test_bench_configuration_full_library(lgmod):
     T = w.angle_samples
     kw = dict(sweeps=w.sweeps, top_k=w.top_k, trans_samples=T, trans_step=oracle.trans_step(T),
               clash_dist2=oracle.CLASH2)
-    sub = L.subset(np.arange(4000))
-    lg.lg_autotune(pocket, lg.device_ligands(sub.atom_offset, sub.tors_offset, sub.x, sub.y, sub.z, sub.frag_mask,
-                                             sub.tors_atoms, sub.inv_bond_len, sub.ref_point), rt, at, **kw)
+    import bench
+    spec = bench.DEFAULT_TUNING
     t = pocket.get_tuning()
-    say(f"bench configuration: {L.n} ligands, tuned atom bounds {list(t.atom_bounds[:t.n_atom_clusters])}")
+    t.n_atom_clusters = len(spec["atom_bounds"])
+    for c, b in enumerate(spec["atom_bounds"]):
+        t.atom_bounds[c] = b
+    t.n_rot_clusters = len(spec["rot_bounds"])
+    for c, b in enumerate(spec["rot_bounds"]):
+        t.rot_bounds[c] = b
+    for c, v in enumerate(spec["waves_per_block"]):
+        t.waves_per_block[c] = v
+    t.restart_chunk, t.grid_scale, t.lazy_clash = spec["restart_chunk"], spec["grid_scale"], spec["lazy_clash"]
+    pocket.set_tuning(t)
+    say(f"bench configuration: {L.n} ligands, {bench.tuning_key(pocket.get_tuning())}")
     dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
                            L.inv_bond_len, L.ref_point)
     out = lg.lg_dock_batch(pocket, dl, rt, at, want_all_scores=True, **kw)
