@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_checks.h"
@@ -660,12 +661,16 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     const char* h = host[t % 2];
     const size_t nk = (size_t)(c.c1 - c.c0) * k;
     const size_t a0 = (size_t)H->atom_offset[c.c0], na = (size_t)H->atom_offset[c.c1] - a0;
+    // the pose coordinates (most of the bytes, often into pages the caller has
+    // not touched yet) in three threads
+    std::thread ty([&] { std::memcpy(O->y + k * a0, h + o_oy, (size_t)k * na * 4); });
+    std::thread tz([&] { std::memcpy(O->z + k * a0, h + o_oz, (size_t)k * na * 4); });
+    std::memcpy(O->x + k * a0, h + o_ox, (size_t)k * na * 4);
     std::memcpy(O->score + (size_t)c.c0 * k, h + o_sc, nk * 4);
     std::memcpy(O->restart_id + (size_t)c.c0 * k, h + o_rid, nk * 4);
     if (O->pivot) std::memcpy(O->pivot + (size_t)c.c0 * k * 3, h + o_piv, nk * 12);
-    std::memcpy(O->x + k * a0, h + o_ox, (size_t)k * na * 4);
-    std::memcpy(O->y + k * a0, h + o_oy, (size_t)k * na * 4);
-    std::memcpy(O->z + k * a0, h + o_oz, (size_t)k * na * 4);
+    ty.join();
+    tz.join();
     if (O->chunk_done) {
       std::atomic_thread_fence(std::memory_order_release);   // outputs before the entry
       reinterpret_cast<volatile int32_t*>(O->chunk_done)[todo[t]] = 1;
@@ -684,11 +689,8 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     const int sl = ci % 2;
     char* h = host[sl];
     char* d = dev[sl];
-    // the slot's previous chunk must be back on the host before its staging is reused
-    if (ci >= 2) {
-      if (hipEventSynchronize(ev_out[sl]) != hipSuccess) { s = fail(LG_ERR_DEVICE, "stream copy-back failed"); break; }
-      unpack(ci - 2);
-    }
+    // the slot's previous chunk (ci - 2) was unpacked after chunk ci - 1 was
+    // enqueued, so its staging is free
     // pack: offsets rebased to the chunk, arrays copied into pinned staging
     const int n = c.c1 - c.c0;
     const int a0 = H->atom_offset[c.c0], na = H->atom_offset[c.c1] - a0;
@@ -762,14 +764,21 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     if (e == hipSuccess) e = hipEventRecord(ev_out[sl], cout);
     if (e != hipSuccess) { s = fail(LG_ERR_DEVICE, "stream copy-out failed: %s", hipGetErrorString(e)); break; }
     enq = ci + 1;
-  }
-  // the last two chunks enqueued
-  for (int ci = std::max(0, enq - 2); ci < enq && s == LG_OK; ++ci) {
-    if (hipEventSynchronize(ev_out[ci % 2]) != hipSuccess) {
-      s = fail(LG_ERR_DEVICE, "stream copy-back failed");
-      break;
+    // the previous chunk's results into the caller's arrays while this one docks
+    if (ci >= 1) {
+      if (hipEventSynchronize(ev_out[(ci - 1) % 2]) != hipSuccess) {
+        s = fail(LG_ERR_DEVICE, "stream copy-back failed");
+        break;
+      }
+      unpack(ci - 1);
     }
-    unpack(ci);
+  }
+  // the last chunk enqueued
+  if (s == LG_OK && enq >= 1) {
+    if (hipEventSynchronize(ev_out[(enq - 1) % 2]) != hipSuccess)
+      s = fail(LG_ERR_DEVICE, "stream copy-back failed");
+    else
+      unpack(enq - 1);
   }
   release();
   if (s == LG_OK && enq < nc)
