@@ -468,6 +468,27 @@ def test_degenerate_cases(lgmod, tiny):
                 start, P0 = oracle.place(sub.ligand(i), tiny["r32"][r].astype(np.float64),
                                          pk.center.astype(np.float64), bits=32)
                 np.testing.assert_array_equal(ref["poses"][r], start)
+    # refinement with no steps returns every pose unchanged with its trilinear
+    # score (one and two poses per wavefront)
+    dl = lg.device_ligands(sub.atom_offset, sub.tors_offset, sub.x, sub.y, sub.z, sub.frag_mask, sub.tors_atoms,
+                           sub.inv_bond_len, sub.ref_point)
+    for k in (1, 2):
+        out = lg.lg_dock_batch(pocket, dl, rt, at, sweeps=w.sweeps, top_k=k, trans_samples=w.angle_samples,
+                               trans_step=oracle.trans_step(w.angle_samples), clash_dist2=oracle.CLASH2)
+        poses = lg.docked_poses(dl, out)
+        res = lg.lg_refine(pocket, poses, lg.refine_params(steps=0, clash_dist2=oracle.CLASH2, poses_per_ligand=k))
+        torch.cuda.synchronize()
+        h = {key: v.cpu().numpy() for key, v in out.items()}
+        r = {key: v.cpu().numpy() for key, v in res.items()}
+        for c in ("x", "y", "z"):
+            np.testing.assert_array_equal(r[c], h[c], err_msg=f"steps = 0, k = {k}: {c}")
+        for i in range(sub.n):
+            for q in range(k):
+                pose = pose_of(h, sub, i, q, k).astype(np.float64)
+                sc, best, acc = oracle.refine(sub.ligand(i), pk, pose, h["pivot"][i, q].astype(np.float64), bits=32,
+                                              steps=0)
+                np.testing.assert_array_equal(best, pose)
+                assert r["score"][i * k + q] == sc and acc == 0
     pocket.free()
 
 
