@@ -76,6 +76,39 @@ def test_ragged_sizes_and_sample_counts(lgmod, tiny, A, T):
     pocket.free()
 
 
+def test_refine_ragged_sizes(lgmod, tiny):
+    """Refinement of ligands of 1 to 256 atoms and 0 to 32 bonds (every kernel
+    size class, two poses per wavefront for the small ones at k = 2): each kept
+    pose refined bit for bit as the FP32 oracle refines it."""
+    lg = lgmod
+    import torch
+    w, pk = tiny["w"], tiny["pocket"]
+    L = ragged_ligands()
+    pocket = device_pocket(pk)
+    rt = torch.from_numpy(tiny["r32"]).cuda()
+    at = torch.from_numpy(tiny["a32"]).cuda()
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, L.x, L.y, L.z, L.frag_mask, L.tors_atoms,
+                           L.inv_bond_len, L.ref_point)
+    for k in (1, 2):
+        say(f"refine ragged: N up to 256, K up to 32, k = {k}")
+        out = lg.lg_dock_batch(pocket, dl, rt, at, sweeps=1, top_k=k, trans_samples=w.angle_samples,
+                               trans_step=oracle.trans_step(w.angle_samples), clash_dist2=oracle.CLASH2)
+        res = lg.lg_refine(pocket, lg.docked_poses(dl, out),
+                           lg.refine_params(steps=20, clash_dist2=oracle.CLASH2, poses_per_ligand=k))
+        torch.cuda.synchronize()
+        h = {key: v.cpu().numpy() for key, v in out.items()}
+        r = {key: v.cpu().numpy() for key, v in res.items()}
+        for i in range(L.n):
+            lig = L.ligand(i)
+            for q in range(k):
+                pose = pose_of(h, L, i, q, k).astype(np.float64)
+                sc, best, _ = oracle.refine(lig, pk, pose, h["pivot"][i, q].astype(np.float64), bits=32, steps=20)
+                np.testing.assert_array_equal(pose_of(r, L, i, q, k).astype(np.float64), best,
+                                              err_msg=f"k={k}: ligand {i} (N={L.n_atoms[i]}, K={L.n_tors[i]}) pose {q}")
+                assert r["score"][i * k + q] == sc, (k, i, q)
+    pocket.free()
+
+
 def test_full_size_mixed_sampled(lgmod):
     """Mixed workload at full per-ligand size (96^3 grid, R=256, A=T=256, S=3, top-10) in
     the bucketed launch; sampled restarts checked against the oracle one by one."""
