@@ -27,8 +27,10 @@
  *    kernel checks the device copies and its counters are read back before the
  *    docking work (one stream synchronisation).
  *    HIP errors map to LG_ERR_DEVICE and are reported by the call that
- *    observes them.  lg_last_error() gives a
- *    message for the last failing call of the calling thread.
+ *    observes them; a host allocation the library cannot make (its staging,
+ *    plans, chunk lists) returns LG_ERR_OUT_OF_MEMORY.  lg_last_error() gives
+ *    a message (at most 511 characters) for the last failing call of the
+ *    calling thread.
  *  - Coordinates are Angstrom, FP32.  Arithmetic is FP32 with explicit fma
  *    (no contraction); given the same inputs, results are bitwise
  *    reproducible run to run and identical between LG_PLAIN and LG_BUCKETED.

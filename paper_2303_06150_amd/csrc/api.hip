@@ -10,7 +10,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <string>
+#include <memory>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -58,6 +59,7 @@ using lghost::workspace_limit;
 using lghost::check_ligands;
 using lghost::host_maxima;
 using lghost::check_host_ligands;
+using lghost::guarded;
 
 #define LG_HIP(call)                                                                          \
   do {                                                                                        \
@@ -228,14 +230,20 @@ lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t 
     if (lg::launch_pad(grid, nx, ny, nz, desc->out_value, p->padded, st) != hipSuccess)
       s = fail(LG_ERR_DEVICE, "pad kernel launch failed");
   } else {
-    std::vector<float> h(padded, desc->out_value);
-    for (int z = 0; z < nz; ++z)
-      for (int y = 0; y < ny; ++y)
-        std::memcpy(&h[((size_t)(z + 1) * (ny + 2) + (y + 1)) * (nx + 2) + 1], &grid[((size_t)z * ny + y) * nx],
-                    nx * sizeof(float));
-    if (hipMemcpyAsync(p->padded, h.data(), padded * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      s = fail(LG_ERR_DEVICE, "grid upload failed");
+    std::unique_ptr<float[]> h(new (std::nothrow) float[padded]);
+    if (!h) {
+      s = fail(LG_ERR_OUT_OF_MEMORY, "host copy of the padded grid (%zu bytes) could not be allocated",
+               padded * sizeof(float));
+    } else {
+      std::fill(h.get(), h.get() + padded, desc->out_value);
+      for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+          std::memcpy(&h[((size_t)(z + 1) * (ny + 2) + (y + 1)) * (nx + 2) + 1], &grid[((size_t)z * ny + y) * nx],
+                      nx * sizeof(float));
+      if (hipMemcpyAsync(p->padded, h.get(), padded * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        s = fail(LG_ERR_DEVICE, "grid upload failed");
+    }
   }
   const int nbx = (nx + 2 + 3) / 4, nby = (ny + 2 + 3) / 4, nbz = (nz + 2 + 1) / 2;
   const size_t nbrick = (size_t)nbx * nby * nbz * 32;
@@ -278,6 +286,7 @@ lg_status lg_load_pocket(const lg_pocket_desc* desc, const float* grid, int32_t 
   G.tab_len = (nx + 2) + (ny + 2) + (nz + 2);
   if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) {
     (void)hipFree(p->padded);
+    (void)hipFree(p->brick);
     delete p;
     return fail(LG_ERR_DEVICE, "stream creation failed");
   }
@@ -515,7 +524,7 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
     if (s != LG_OK) return s;
     hipError_t e = enqueue(launches, st, true);
     if (e != hipSuccess) return fail(LG_ERR_DEVICE, "bucketed launch failed: %s", hipGetErrorString(e));
-    p->launches = launches;
+    p->launches = std::move(launches);
     p->counts_dev = counts;
     p->timed = true;
     return LG_OK;
@@ -544,8 +553,8 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
       p->gexec = nullptr;
       return fail(LG_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e3));
     }
-    p->gkey = key;
-    p->launches = launches;
+    p->gkey = std::move(key);
+    p->launches = std::move(launches);
     p->counts_dev = counts;
   }
   p->timed = false;
@@ -558,11 +567,15 @@ extern "C" {
 
 lg_status lg_dock_batch(lg_pocket p, const lg_ligands* L, const lg_dock_params* P, const lg_dock_out* O,
                         void* stream) {
-  return dock_batch_impl(p, L, P, O, stream, -1, -1, false);
+  return guarded([&] { return dock_batch_impl(p, L, P, O, stream, -1, -1, false); });
 }
 
-lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_params* P, int32_t chunk,
-                         const lg_host_out* O, void* stream) {
+}  // extern "C"
+
+namespace {
+
+lg_status dock_stream_impl(lg_pocket p, const lg_host_ligands* H, const lg_dock_params* P, int32_t chunk,
+                           const lg_host_out* O, void* stream) {
   if (!p || !P || !O) return fail(LG_ERR_INVALID_ARG, "pocket, params and out must not be NULL");
   lg_status s = check_host_ligands(H);
   if (s != LG_OK) return s;
@@ -662,15 +675,27 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     const size_t nk = (size_t)(c.c1 - c.c0) * k;
     const size_t a0 = (size_t)H->atom_offset[c.c0], na = (size_t)H->atom_offset[c.c1] - a0;
     // the pose coordinates (most of the bytes, often into pages the caller has
-    // not touched yet) in three threads
-    std::thread ty([&] { std::memcpy(O->y + k * a0, h + o_oy, (size_t)k * na * 4); });
-    std::thread tz([&] { std::memcpy(O->z + k * a0, h + o_oz, (size_t)k * na * 4); });
+    // not touched yet) in three threads; a copy whose thread cannot start runs
+    // here
+    auto cy = [&] { std::memcpy(O->y + k * a0, h + o_oy, (size_t)k * na * 4); };
+    auto cz = [&] { std::memcpy(O->z + k * a0, h + o_oz, (size_t)k * na * 4); };
+    std::thread ty, tz;
+    try {
+      ty = std::thread(cy);
+    } catch (...) {
+      cy();
+    }
+    try {
+      tz = std::thread(cz);
+    } catch (...) {
+      cz();
+    }
     std::memcpy(O->x + k * a0, h + o_ox, (size_t)k * na * 4);
     std::memcpy(O->score + (size_t)c.c0 * k, h + o_sc, nk * 4);
     std::memcpy(O->restart_id + (size_t)c.c0 * k, h + o_rid, nk * 4);
     if (O->pivot) std::memcpy(O->pivot + (size_t)c.c0 * k * 3, h + o_piv, nk * 12);
-    ty.join();
-    tz.join();
+    if (ty.joinable()) ty.join();
+    if (tz.joinable()) tz.join();
     if (O->chunk_done) {
       std::atomic_thread_fence(std::memory_order_release);   // outputs before the entry
       reinterpret_cast<volatile int32_t*>(O->chunk_done)[todo[t]] = 1;
@@ -750,7 +775,7 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
     DO.z = (float*)(d + o_oz);
     lg_dock_params DP = *P;
     DP.mode = LG_BUCKETED;
-    s = dock_batch_impl(p, &L, &DP, &DO, cs, c.max_atoms, c.max_tors, true);
+    s = guarded([&] { return dock_batch_impl(p, &L, &DP, &DO, cs, c.max_atoms, c.max_tors, true); });
     if (s != LG_OK) break;
     e = hipEventRecord(ev_dock[sl], cs);
     // copy the results out behind the docking
@@ -786,8 +811,8 @@ lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_pa
   return s;
 }
 
-lg_status lg_dock_sites(const lg_pocket* pockets, int32_t n_sites, const lg_ligands* L, const lg_dock_params* P,
-                        const lg_dock_out* outs, int32_t site_major, void* stream) {
+lg_status dock_sites_impl(const lg_pocket* pockets, int32_t n_sites, const lg_ligands* L, const lg_dock_params* P,
+                          const lg_dock_out* outs, int32_t site_major, void* stream) {
   if (!pockets || !P || !outs) return fail(LG_ERR_INVALID_ARG, "pockets, params and outs must not be NULL");
   if (n_sites < 1 || n_sites > 4096) return fail(LG_ERR_INVALID_ARG, "n_sites %d outside 1..4096", n_sites);
   for (int si = 0; si < n_sites; ++si) {
@@ -923,18 +948,33 @@ lg_status lg_dock_sites(const lg_pocket* pockets, int32_t n_sites, const lg_liga
   return LG_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+lg_status lg_dock_stream(lg_pocket p, const lg_host_ligands* H, const lg_dock_params* P, int32_t chunk,
+                         const lg_host_out* O, void* stream) {
+  return guarded([&] { return dock_stream_impl(p, H, P, chunk, O, stream); });
+}
+
+lg_status lg_dock_sites(const lg_pocket* pockets, int32_t n_sites, const lg_ligands* L, const lg_dock_params* P,
+                        const lg_dock_out* outs, int32_t site_major, void* stream) {
+  return guarded([&] { return dock_sites_impl(pockets, n_sites, L, P, outs, site_major, stream); });
+}
+
 int32_t lg_bucket_stats(lg_pocket p, lg_bucket_stat* out, int32_t capacity) {
   if (!p) return fail(LG_ERR_INVALID_ARG, "pocket is NULL");
   const int nl = (int)p->launches.size();
   if (!out || capacity <= 0 || nl == 0) return nl;
   if (hipDeviceSynchronize() != hipSuccess) return fail(LG_ERR_DEVICE, "device synchronise failed");
-  std::vector<int32_t> counts(p->tuning.n_atom_clusters * p->tuning.n_rot_clusters, 0);
+  int32_t counts[16 * 32] = {};   // at most 16 atom x 32 rotamer clusters
+  const int nb = p->tuning.n_atom_clusters * p->tuning.n_rot_clusters;
   if (p->counts_dev &&
-      hipMemcpy(counts.data(), p->counts_dev, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(counts, p->counts_dev, (size_t)nb * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(LG_ERR_DEVICE, "reading bucket counts failed");
   for (int l = 0; l < nl && l < capacity; ++l) {
     out[l] = p->launches[l];
-    if (p->launches[l].bucket < (int)counts.size()) out[l].ligands = counts[p->launches[l].bucket];
+    if (p->launches[l].bucket < nb) out[l].ligands = counts[p->launches[l].bucket];
     float ms = -1.f, span = -1.f;
     if (p->timed && (hipEventElapsedTime(&ms, p->events[1 + 2 * l], p->events[2 + 2 * l]) != hipSuccess ||
                      hipEventElapsedTime(&span, p->events[0], p->events[1 + 2 * nl]) != hipSuccess)) {

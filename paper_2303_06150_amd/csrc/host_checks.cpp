@@ -7,19 +7,18 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
-#include <string>
 
 namespace lghost {
 
-thread_local std::string g_err;
+// The last error message of the calling thread; a fixed buffer, so recording
+// an error never allocates (it may be the report of a failed allocation).
+thread_local char g_err[512];
 
 lg_status fail(lg_status s, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return s;
 }
 
@@ -153,7 +152,7 @@ using lghost::g_err;
 
 extern "C" {
 
-const char* lg_last_error(void) { return g_err.c_str(); }
+const char* lg_last_error(void) { return g_err; }
 
 int32_t lg_version(void) { return 1; }
 

@@ -6,6 +6,8 @@
 // through fail(), which records the message lg_last_error() returns.
 #pragma once
 #include <cstddef>
+#include <exception>
+#include <new>
 
 #include "lg.h"
 
@@ -24,5 +26,23 @@ void host_maxima(const lg_ligands* L, int* max_atoms, int* max_tors);
 // A host-resident library (lg_dock_stream): the device check's rules, on the host.
 lg_status check_host_ligands(const lg_host_ligands* H);
 lg_status check_tuning(const lg_tuning* t);
+
+// No C++ exception crosses the C ABI: a host allocation that fails inside a
+// call (std::bad_alloc) becomes LG_ERR_OUT_OF_MEMORY, anything else thrown
+// LG_ERR_DEVICE, with the message recorded.  A guarded body that throws must
+// leave no device memory that its pocket does not own and free nothing the
+// device may still be using.
+template <class F>
+auto guarded(F&& f) noexcept -> decltype(f()) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(LG_ERR_OUT_OF_MEMORY, "host memory could not be allocated");
+  } catch (const std::exception& e) {
+    return fail(LG_ERR_DEVICE, "host-side failure: %s", e.what());
+  } catch (...) {
+    return fail(LG_ERR_DEVICE, "host-side failure");
+  }
+}
 
 }  // namespace lghost

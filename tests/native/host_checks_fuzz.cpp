@@ -9,6 +9,8 @@
 #include <cstring>
 #include <memory>
 #include <random>
+#include <stdexcept>
+#include <string>
 #include <algorithm>
 #include <vector>
 
@@ -156,6 +158,19 @@ int main() {
   EXPECT(lg_bucket_size(16, 108, 32, 32) == 1728, "Eq. 1");
   EXPECT(lg_bucket_size(1, 1, 0, 64) == -1, "Eq. 1 bad args");
   EXPECT(lghost::check_ligands(nullptr, true) == LG_ERR_INVALID_ARG, "null batch");
+  // the error message lives in a fixed buffer: a longer one is cut, terminated
+  std::string long_msg(2000, 'm');
+  EXPECT(lghost::fail(LG_ERR_LIMIT, "%s", long_msg.c_str()) == LG_ERR_LIMIT, "fail returns its status");
+  EXPECT(std::strlen(lg_last_error()) == 511 && lg_last_error()[0] == 'm', "long message not cut at 511");
+  EXPECT(lghost::fail(LG_ERR_INVALID_ARG, "short %d", 7) == LG_ERR_INVALID_ARG &&
+         std::strcmp(lg_last_error(), "short 7") == 0, "short message after a long one");
+  // exceptions stop at the boundary as status codes, results pass through
+  EXPECT(lghost::guarded([] { return LG_ERR_LIMIT; }) == LG_ERR_LIMIT, "guarded result");
+  EXPECT(lghost::guarded([]() -> lg_status { throw std::bad_alloc(); }) == LG_ERR_OUT_OF_MEMORY &&
+         std::strstr(lg_last_error(), "host memory") != nullptr, "bad_alloc not mapped");
+  EXPECT(lghost::guarded([]() -> lg_status { throw std::runtime_error("thread start"); }) == LG_ERR_DEVICE &&
+         std::strstr(lg_last_error(), "thread start") != nullptr, "exception not mapped");
+  EXPECT(lghost::guarded([]() -> lg_status { throw 3; }) == LG_ERR_DEVICE, "non-exception throw not mapped");
   std::printf("host checks: %d planted defects reported, no sanitizer findings\n", rejected);
   return 0;
 }
