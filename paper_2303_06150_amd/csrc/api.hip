@@ -488,6 +488,7 @@ lg_status dock_batch_impl(lg_pocket p, const lg_ligands* L, const lg_dock_params
       }
     }
     const size_t nl = launches.size();
+    p->events.reserve(2 * nl + 2);   // a failed allocation throws here, before an event exists
     while (p->events.size() < 2 * nl + 2) {
       hipEvent_t ev;
       LG_HIP(hipEventCreate(&ev));
