@@ -8,7 +8,9 @@ carry many atoms out of the box (nearest node clamped to the border, far
 value), and refinement moves atoms across the edge of the trilinear range (far
 value, zero gradient).  Every ligand's docking trace, scores, top-k poses and
 pivots, and the refinement of its kept poses with one and with two poses per
-wavefront, must equal the FP32 oracle's bitwise.
+wavefront, must equal the FP32 oracle's bitwise; so must the scores of poses
+placed across the low-x and the high-z faces, with their adjoint checked
+against the FP64 oracle.
 """
 import dataclasses
 
@@ -91,4 +93,52 @@ def test_refine_at_the_box_edge_with_far_value(lgmod, tiny, border, k):
     say(f"refined at the box edge (k = {k}): {moved} poses moved, {outside} with atoms outside the box")
     assert moved > L.n * k // 2
     assert outside > 0
+    pocket.free()
+
+
+def test_score_and_adjoint_across_the_box_faces(lgmod, tiny, border):
+    """lg_score on poses that straddle the low-x face (the moved box) or the
+    high-z face: nearest and trilinear scores equal the FP32 oracle's bitwise
+    (atoms outside take the far value), the adjoint at zero moves the FP64
+    oracle's to 1e-4 of its largest component (zero gradient outside the
+    trilinear range)."""
+    lg = lgmod
+    import torch
+    pk, L = border, tiny["ligs"]
+    pocket = device_pocket(pk)
+    rng = np.random.default_rng(11)
+    hi_z = pk.origin[2] + (pk.grid.shape[0] - 1) * pk.spacing
+    shift = np.repeat(pk.center[None].astype(np.float64), L.n, 0)
+    low = np.arange(L.n) % 2 == 0
+    shift[low, 0] = pk.origin[0] + rng.uniform(-2, 2, size=low.sum())
+    shift[~low, 2] = hi_z + rng.uniform(-2, 2, size=(~low).sum())
+    shift = shift.astype(np.float32)
+    lig_of = np.repeat(np.arange(L.n), L.n_atoms)
+    cen = np.stack([L.ref_point[0::3], L.ref_point[1::3], L.ref_point[2::3]], 1)
+    xs = (L.x - cen[lig_of, 0] + shift[lig_of, 0]).astype(np.float32)
+    ys = (L.y - cen[lig_of, 1] + shift[lig_of, 1]).astype(np.float32)
+    zs = (L.z - cen[lig_of, 2] + shift[lig_of, 2]).astype(np.float32)
+    outside = (xs < pk.origin[0]) | (zs > hi_z)
+    inside = ~outside
+    per_lig_out = np.bincount(lig_of, weights=outside, minlength=L.n)
+    per_lig_in = np.bincount(lig_of, weights=inside, minlength=L.n)
+    assert ((per_lig_out > 0) & (per_lig_in > 0)).mean() > 0.5   # most poses straddle a face
+    dl = lg.device_ligands(L.atom_offset, L.tors_offset, xs, ys, zs, L.frag_mask, L.tors_atoms,
+                           L.inv_bond_len, shift.reshape(-1))
+    say("lg_score across the box faces, far value -0.75")
+    near = lg.lg_score(pocket, dl, lg.LG_NEAREST)["score"].cpu().numpy()
+    tri = lg.lg_score(pocket, dl, lg.LG_TRILINEAR, grad=True)
+    torch.cuda.synchronize()
+    ts, tg = tri["score"].cpu().numpy(), tri["grad"].cpu().numpy()
+    worst = 0.0
+    for i in range(L.n):
+        a0, a1 = L.atom_offset[i], L.atom_offset[i + 1]
+        xyz = np.stack([xs[a0:a1], ys[a0:a1], zs[a0:a1]], 1).astype(np.float64)
+        assert near[i] == oracle.score(pk, xyz, 0, 32), i
+        assert ts[i] == oracle.score(pk, xyz, 1, 32), i
+        _, g64 = oracle.pose_grad(L.ligand(i), pk, xyz, shift[i].astype(np.float64))
+        K = int(L.n_tors[i])
+        g = tg[6 * i + L.tors_offset[i]: 6 * i + L.tors_offset[i] + 6 + K]
+        worst = max(worst, np.abs(g - g64).max() / max(np.abs(g64).max(), 1e-3))
+    assert worst < 1e-4, worst
     pocket.free()
