@@ -676,27 +676,35 @@ lg_status dock_stream_impl(lg_pocket p, const lg_host_ligands* H, const lg_dock_
     const size_t nk = (size_t)(c.c1 - c.c0) * k;
     const size_t a0 = (size_t)H->atom_offset[c.c0], na = (size_t)H->atom_offset[c.c1] - a0;
     // the pose coordinates (most of the bytes, often into pages the caller has
-    // not touched yet) in three threads; a copy whose thread cannot start runs
-    // here
-    auto cy = [&] { std::memcpy(O->y + k * a0, h + o_oy, (size_t)k * na * 4); };
-    auto cz = [&] { std::memcpy(O->z + k * a0, h + o_oz, (size_t)k * na * 4); };
-    std::thread ty, tz;
-    try {
-      ty = std::thread(cy);
-    } catch (...) {
-      cy();
+    // not touched yet) in page-aligned slices of at least 1 MB per array, one
+    // thread per slice beyond the first (up to eight slices); a slice whose
+    // thread cannot start is copied here
+    const size_t pose_bytes = (size_t)k * na * 4;
+    char* dst[3] = {(char*)(O->x + k * a0), (char*)(O->y + k * a0), (char*)(O->z + k * a0)};
+    const char* src[3] = {h + o_ox, h + o_oy, h + o_oz};
+    constexpr int kMaxSlices = 8;
+    const int slices = (int)std::max<size_t>(1, std::min<size_t>(kMaxSlices, pose_bytes >> 20));
+    auto slice = [&](int t) {
+      for (int d = 0; d < 3; ++d) {
+        const size_t b0 = std::min(pose_bytes, (pose_bytes / slices * t) & ~(size_t)4095);
+        const size_t b1 = t == slices - 1 ? pose_bytes : std::min(pose_bytes, (pose_bytes / slices * (t + 1)) & ~(size_t)4095);
+        if (b1 > b0) std::memcpy(dst[d] + b0, src[d] + b0, b1 - b0);
+      }
+    };
+    std::thread th[kMaxSlices - 1];
+    for (int t = 1; t < slices; ++t) {
+      try {
+        th[t - 1] = std::thread(slice, t);
+      } catch (...) {
+        slice(t);
+      }
     }
-    try {
-      tz = std::thread(cz);
-    } catch (...) {
-      cz();
-    }
-    std::memcpy(O->x + k * a0, h + o_ox, (size_t)k * na * 4);
+    slice(0);
     std::memcpy(O->score + (size_t)c.c0 * k, h + o_sc, nk * 4);
     std::memcpy(O->restart_id + (size_t)c.c0 * k, h + o_rid, nk * 4);
     if (O->pivot) std::memcpy(O->pivot + (size_t)c.c0 * k * 3, h + o_piv, nk * 12);
-    if (ty.joinable()) ty.join();
-    if (tz.joinable()) tz.join();
+    for (std::thread& t : th)
+      if (t.joinable()) t.join();
     if (O->chunk_done) {
       std::atomic_thread_fence(std::memory_order_release);   // outputs before the entry
       reinterpret_cast<volatile int32_t*>(O->chunk_done)[todo[t]] = 1;
