@@ -684,27 +684,27 @@ lg_status dock_stream_impl(lg_pocket p, const lg_host_ligands* H, const lg_dock_
     const char* src[3] = {h + o_ox, h + o_oy, h + o_oz};
     constexpr int kMaxSlices = 8;
     const int slices = (int)std::max<size_t>(1, std::min<size_t>(kMaxSlices, pose_bytes >> 20));
-    auto slice = [&](int t) {
+    auto slice = [&](int s) {
       for (int d = 0; d < 3; ++d) {
-        const size_t b0 = std::min(pose_bytes, (pose_bytes / slices * t) & ~(size_t)4095);
-        const size_t b1 = t == slices - 1 ? pose_bytes : std::min(pose_bytes, (pose_bytes / slices * (t + 1)) & ~(size_t)4095);
+        const size_t b0 = std::min(pose_bytes, (pose_bytes / slices * s) & ~(size_t)4095);
+        const size_t b1 = s == slices - 1 ? pose_bytes : std::min(pose_bytes, (pose_bytes / slices * (s + 1)) & ~(size_t)4095);
         if (b1 > b0) std::memcpy(dst[d] + b0, src[d] + b0, b1 - b0);
       }
     };
     std::thread th[kMaxSlices - 1];
-    for (int t = 1; t < slices; ++t) {
+    for (int s = 1; s < slices; ++s) {
       try {
-        th[t - 1] = std::thread(slice, t);
+        th[s - 1] = std::thread(slice, s);
       } catch (...) {
-        slice(t);
+        slice(s);
       }
     }
     slice(0);
     std::memcpy(O->score + (size_t)c.c0 * k, h + o_sc, nk * 4);
     std::memcpy(O->restart_id + (size_t)c.c0 * k, h + o_rid, nk * 4);
     if (O->pivot) std::memcpy(O->pivot + (size_t)c.c0 * k * 3, h + o_piv, nk * 12);
-    for (std::thread& t : th)
-      if (t.joinable()) t.join();
+    for (std::thread& w : th)
+      if (w.joinable()) w.join();
     if (O->chunk_done) {
       std::atomic_thread_fence(std::memory_order_release);   // outputs before the entry
       reinterpret_cast<volatile int32_t*>(O->chunk_done)[todo[t]] = 1;
