@@ -623,7 +623,6 @@ lg_status dock_stream_impl(lg_pocket p, const lg_host_ligands* H, const lg_dock_
   const size_t o_z = lay.take((size_t)cap_atoms * 4), o_mask = lay.take((size_t)cap_atoms * 4);
   const size_t o_tat = lay.take((size_t)2 * cap_tors * 4 + 4), o_il = lay.take((size_t)cap_tors * 4 + 4);
   const size_t o_ref = lay.take((size_t)3 * cap_n * 4);
-  const size_t in_bytes = lay.off;
   const size_t o_sc = lay.take((size_t)cap_n * k * 4), o_rid = lay.take((size_t)cap_n * k * 4);
   const size_t o_piv = lay.take((size_t)3 * cap_n * k * 4);
   const size_t o_ox = lay.take((size_t)k * cap_atoms * 4), o_oy = lay.take((size_t)k * cap_atoms * 4);
