@@ -4,7 +4,6 @@ import ctypes
 import os
 import re
 
-import pytest
 
 from paper_2303_06150_amd import lg
 

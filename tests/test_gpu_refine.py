@@ -5,7 +5,6 @@ torch.autograd.Function wrapper."""
 import numpy as np
 import pytest
 
-import gen
 import oracle
 from gpu_common import device_pocket, dock_gpu
 

@@ -6,7 +6,6 @@ linear grids."""
 import numpy as np
 import pytest
 
-import gen
 import oracle
 from conftest import topo_distances
 from test_oracle_pins import make_pocket
