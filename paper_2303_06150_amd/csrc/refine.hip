@@ -229,6 +229,7 @@ constexpr int TILE_FLOATS = TILE_COLS * TILE_STRIDE;
 constexpr int GRAD_COLS = 7 + 3 * 32;              // score, force, torque, 3 per bond
 constexpr int GRAD_RES_FLOATS = 104;               // GRAD_COLS rounded up to float4
 constexpr int GRAD_LDS_FLOAT4 = (TILE_FLOATS + GRAD_RES_FLOATS) / 4;
+static_assert(GRAD_RES_FLOATS >= GRAD_COLS && GRAD_RES_FLOATS % 4 == 0, "gradient results: every column, whole float4");
 static_assert(TILE_FLOATS >= 12 * 32, "the torsion matrices reuse the tile");
 
 // Trilinear score and its gradient with respect to the local move at zero;
@@ -507,18 +508,18 @@ __global__ __launch_bounds__(256) void refine_kernel(GridDev G, LigDev P, Refine
       float4* mats = reinterpret_cast<float4*>(tile) + refine_mats_float4(NSLOT);
       const float w2 = fmaf(q[5], q[5], fmaf(q[4], q[4], q[3] * q[3]));
       const bool rot = w2 > 0.f;
-      float w = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+      float wlen = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
       if (rot) {
-        w = sqrtf(w2);
+        wlen = sqrtf(w2);
         const float num = lane == 0 ? q[3] : (lane == 1 ? q[4] : q[5]);
-        const float u = num / w;
+        const float u = num / wlen;
         wx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 0));
         wy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 1));
         wz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 2));
       }
       const bool bond = lane < K && thk != 0.f;
       if (bond || (lane == K && rot)) {
-        const float ang = bond ? thk : w;
+        const float ang = bond ? thk : wlen;
         const float ux = bond ? ax.ux : wx, uy = bond ? ax.uy : wy, uz = bond ? ax.uz : wz;
         float c, sn, m[9];
         step_cos_sin(ang, c, sn);
@@ -829,16 +830,16 @@ __global__ __launch_bounds__(256) void refine_pair_kernel(GridDev G, LigDev P, R
     if (table) {
       // lane 32 h + k < K: bond k's matrix of pose h; lane 32 h + K: the rigid rotation's
       float4* mats = reinterpret_cast<float4*>(tile_h);
-      float w = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+      float wlen = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
       if (rot) {
-        w = sqrtf(w2);
-        wx = q[3] / w;
-        wy = q[4] / w;
-        wz = q[5] / w;
+        wlen = sqrtf(w2);
+        wx = q[3] / wlen;
+        wy = q[4] / wlen;
+        wz = q[5] / wlen;
       }
       const bool bond = la < K && thk != 0.f;
       if (bond || (la == K && rot)) {
-        const float ang = bond ? thk : w;
+        const float ang = bond ? thk : wlen;
         const float ux = bond ? ax.ux : wx, uy = bond ? ax.uy : wy, uz = bond ? ax.uz : wz;
         float c, sn, mm[9];
         step_cos_sin(ang, c, sn);
@@ -900,10 +901,10 @@ __global__ __launch_bounds__(256) void refine_pair_kernel(GridDev G, LigDev P, R
         }
       }
       if (rot) {
-        const float w = sqrtf(w2);
+        const float wlen = sqrtf(w2);
         float c, sn, mm[9];
-        step_cos_sin(w, c, sn);
-        torsion_matrix(q[3] / w, q[4] / w, q[5] / w, c, sn, mm);
+        step_cos_sin(wlen, c, sn);
+        torsion_matrix(q[3] / wlen, q[4] / wlen, q[5] / wlen, c, sn, mm);
         float y0, y1, y2;
         mat_apply(mm, cand.x[0] - cand.piv[0], cand.x[1] - cand.piv[1], cand.x[2] - cand.piv[2], y0, y1, y2);
         cand.x[0] = cand.piv[0] + y0;
@@ -1038,12 +1039,12 @@ hipError_t launch_score_moves(int nslot, const GridDev& G, const LigDev& P, cons
   if (n == 0) return hipSuccess;
   const int wpb = 4;
   const dim3 grid((n + wpb - 1) / wpb), block(64 * wpb);
-  const size_t lds = (size_t)wpb * (64 * nslot + 32 + GRAD_LDS_FLOAT4) * sizeof(float4);
+  const size_t lds_bytes = (size_t)wpb * (64 * nslot + 32 + GRAD_LDS_FLOAT4) * sizeof(float4);
   switch (nslot) {
-    case 1: hipLaunchKernelGGL(score_moves_kernel<1>, grid, block, lds, st, G, P, moves, n, score, grad); break;
-    case 2: hipLaunchKernelGGL(score_moves_kernel<2>, grid, block, lds, st, G, P, moves, n, score, grad); break;
-    case 3: hipLaunchKernelGGL(score_moves_kernel<3>, grid, block, lds, st, G, P, moves, n, score, grad); break;
-    case 4: hipLaunchKernelGGL(score_moves_kernel<4>, grid, block, lds, st, G, P, moves, n, score, grad); break;
+    case 1: hipLaunchKernelGGL(score_moves_kernel<1>, grid, block, lds_bytes, st, G, P, moves, n, score, grad); break;
+    case 2: hipLaunchKernelGGL(score_moves_kernel<2>, grid, block, lds_bytes, st, G, P, moves, n, score, grad); break;
+    case 3: hipLaunchKernelGGL(score_moves_kernel<3>, grid, block, lds_bytes, st, G, P, moves, n, score, grad); break;
+    case 4: hipLaunchKernelGGL(score_moves_kernel<4>, grid, block, lds_bytes, st, G, P, moves, n, score, grad); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1058,8 +1059,8 @@ hipError_t launch_refine_pair(const GridDev& G, const LigDev& P, const RefineDev
   if (waves == 0) return hipSuccess;
   const int wpb = 4;
   const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(64 * wpb);
-  const size_t lds = (size_t)wpb * pair_wave_float4() * sizeof(float4);
-  hipLaunchKernelGGL(refine_pair_kernel, grid, block, lds, st, G, P, Rp, (int)waves);
+  const size_t lds_bytes = (size_t)wpb * pair_wave_float4() * sizeof(float4);
+  hipLaunchKernelGGL(refine_pair_kernel, grid, block, lds_bytes, st, G, P, Rp, (int)waves);
   return hipGetLastError();
 }
 
