@@ -684,11 +684,10 @@ lg_status dock_stream_impl(lg_pocket p, const lg_host_ligands* H, const lg_dock_
     constexpr int kMaxSlices = 8;
     const int slices = (int)std::max<size_t>(1, std::min<size_t>(kMaxSlices, pose_bytes >> 20));
     auto slice = [&](int s) {
-      for (int d = 0; d < 3; ++d) {
-        const size_t b0 = std::min(pose_bytes, (pose_bytes / slices * s) & ~(size_t)4095);
-        const size_t b1 = s == slices - 1 ? pose_bytes : std::min(pose_bytes, (pose_bytes / slices * (s + 1)) & ~(size_t)4095);
-        if (b1 > b0) std::memcpy(dst[d] + b0, src[d] + b0, b1 - b0);
-      }
+      size_t b0, b1;
+      lghost::copy_slice(pose_bytes, slices, s, &b0, &b1);
+      if (b1 > b0)
+        for (int d = 0; d < 3; ++d) std::memcpy(dst[d] + b0, src[d] + b0, b1 - b0);
     };
     std::thread th[kMaxSlices - 1];
     for (int s = 1; s < slices; ++s) {

@@ -146,6 +146,12 @@ lg_status check_tuning(const lg_tuning* t) {
   return LG_OK;
 }
 
+void copy_slice(size_t bytes, int slices, int s, size_t* b0, size_t* b1) {
+  const size_t per = bytes / (size_t)slices;
+  *b0 = std::min(bytes, (per * (size_t)s) & ~(size_t)4095);
+  *b1 = s == slices - 1 ? bytes : std::min(bytes, (per * (size_t)(s + 1)) & ~(size_t)4095);
+}
+
 }  // namespace lghost
 
 using lghost::g_err;

@@ -27,6 +27,11 @@ void host_maxima(const lg_ligands* L, int* max_atoms, int* max_tors);
 lg_status check_host_ligands(const lg_host_ligands* H);
 lg_status check_tuning(const lg_tuning* t);
 
+// Byte range [*b0, *b1) of slice s of `slices` page-aligned slices of a
+// `bytes`-long copy (the last slice ends at `bytes`; the slices tile the range
+// in order, some possibly empty).
+void copy_slice(size_t bytes, int slices, int s, size_t* b0, size_t* b1);
+
 // No C++ exception crosses the C ABI: a host allocation that fails inside a
 // call (std::bad_alloc) becomes LG_ERR_OUT_OF_MEMORY, anything else thrown
 // LG_ERR_DEVICE, with the message recorded.  A guarded body that throws must

@@ -164,6 +164,20 @@ int main() {
   EXPECT(std::strlen(lg_last_error()) == 511 && lg_last_error()[0] == 'm', "long message not cut at 511");
   EXPECT(lghost::fail(LG_ERR_INVALID_ARG, "short %d", 7) == LG_ERR_INVALID_ARG &&
          std::strcmp(lg_last_error(), "short 7") == 0, "short message after a long one");
+  // the stream unpack's slices tile every copy in order, starts page-aligned
+  for (size_t bytes : {(size_t)0, (size_t)4, (size_t)4096, (size_t)4100, (size_t)1 << 20, ((size_t)3 << 20) + 77,
+                       (size_t)123456789, (size_t)1 << 33})
+    for (int slices = 1; slices <= 8; ++slices) {
+      size_t pos = 0;
+      for (int s = 0; s < slices; ++s) {
+        size_t b0, b1;
+        lghost::copy_slice(bytes, slices, s, &b0, &b1);
+        EXPECT(b0 <= b1 && (b0 == pos || b0 == b1), "slice %d/%d of %zu: [%zu, %zu) after %zu", s, slices, bytes, b0, b1, pos);
+        EXPECT(b0 == b1 || b0 % 4096 == 0 || s == 0, "slice start not page-aligned");
+        if (b1 > b0) pos = b1;
+      }
+      EXPECT(pos == bytes, "slices of %zu bytes end at %zu", bytes, pos);
+    }
   // exceptions stop at the boundary as status codes, results pass through
   EXPECT(lghost::guarded([] { return LG_ERR_LIMIT; }) == LG_ERR_LIMIT, "guarded result");
   EXPECT(lghost::guarded([]() -> lg_status { throw std::bad_alloc(); }) == LG_ERR_OUT_OF_MEMORY &&
